@@ -1,0 +1,250 @@
+/*
+ * qtt.h -- C ABI of the MI355X (gfx950) library for the quantics-tensor-train
+ * fractional-step method of arxiv 2507.05222 ("Quantum-Inspired Tensor-Network
+ * Fractional-Step Method for Incompressible Flow in Curvilinear Coordinates").
+ *
+ * Every entry point takes plain pointers and sizes; no C++ or torch types cross
+ * this boundary. Device pointers are HIP device allocations owned by the caller;
+ * `stream` is a hipStream_t passed as void* (NULL = the null stream). Calls are
+ * stream-ordered; a call that returns a host scalar synchronises its stream first.
+ *
+ * Return value: QTT_OK (0) or a negative error code. No exception crosses the
+ * ABI. On QTT_EINVAL / QTT_ESHAPE nothing has been launched and no output has
+ * been written. qtt_last_error() gives the message of the last failure of a ctx.
+ *
+ * Data layout (Sec. 2, Eq. simpleMPS / simpleMatrix):
+ *   A TT-vector (MPS) has L cores A[k] of shape (b_k, d, b_{k+1}), b_0 = b_L = 1.
+ *   Core k is stored in slot k of `data`: slot size cap*d*cap doubles, element
+ *   (a, s, c) at data[k*cap*d*cap + a*(d*cap) + s*cap + c]. Entries outside the
+ *   actual bonds are zero (every library kernel that writes a core keeps this).
+ *   `bond` is a DEVICE int32 array of length L+1 with the actual bond dims; the
+ *   library updates it in place and never reallocates.
+ *   The dense vector represented has its entry at index sum_k r_k d^(L-1-k)
+ *   equal to A[0]^{r_0} ... A[L-1]^{r_{L-1}}: core 0 carries the most
+ *   significant digit (App. D). A 2D field f(i, j) on a 2^n x 2^n grid uses the
+ *   interleaved MSB-first bit order i_1 j_1 i_2 j_2 ... (core 2m <- bit m of i,
+ *   core 2m+1 <- bit m of j).
+ *   A TT-matrix (MPO) core has shape (w_k, 2 (out r'), 2 (in r), w_{k+1}) in slots
+ *   of wcap*4*wcap doubles, element (b, r', r, c) at
+ *   data[k*wcap*4*wcap + b*4*wcap + r'*2*wcap + r*wcap + c].
+ */
+#ifndef QTT_H
+#define QTT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  QTT_OK = 0,
+  QTT_EINVAL = -1,       /* bad argument (null pointer, bad enum, bad count)      */
+  QTT_ESHAPE = -2,       /* inconsistent L / d / capacities between operands     */
+  QTT_ECAPACITY = -3,    /* a result needs more than the output capacity allows   */
+  QTT_ENUMERIC = -4,     /* NaN or Inf detected in a result                       */
+  QTT_ENOTCONVERGED = -5,/* solver stopped at max_sweeps above tol; x = best iterate */
+  QTT_EHIP = -6          /* a HIP runtime call failed                              */
+};
+
+/* Arithmetic type of the site contractions (MFMA). Truncation (QR/SVD),
+ * re-orthogonalisation, dot products and residuals are always FP64. */
+typedef enum { QTT_F64 = 0, QTT_F32 = 1, QTT_BF16 = 2 } qtt_dtype;
+
+/* MPS descriptor (host struct holding device pointers). */
+typedef struct {
+  int32_t L;        /* number of cores                                   */
+  int32_t d;        /* physical dimension (2; 4 for an MPO seen as MPS)  */
+  int32_t cap;      /* bond capacity (slot leading dimension)            */
+  int32_t* bond;    /* DEVICE int32[L+1], actual bonds                   */
+  double* data;     /* DEVICE double[L*cap*d*cap]                        */
+} qtt_mps;
+
+/* MPO descriptor. Bonds are fixed at construction and known on the host;
+ * bond_host may hold upper bounds of the device values (it is used for
+ * validation and workspace sizing only). */
+typedef struct {
+  int32_t L;
+  int32_t wcap;             /* slot leading dimension                    */
+  const int32_t* bond_host; /* HOST int32[L+1]                           */
+  const int32_t* bond;      /* DEVICE int32[L+1] (same values)           */
+  const double* data;       /* DEVICE double[L*wcap*4*wcap]              */
+} qtt_mpo;
+
+/* Truncation rule (Sec. 2: "neglecting singular values below a threshold or
+ * selecting the first chi"): per bond, the discarded singular values s_i must
+ * satisfy sqrt(sum s_i^2) <= rel_tol/sqrt(L-1) * ||x|| (so ||x - x~|| <= rel_tol ||x||),
+ * and at most chi_max values are kept (chi_max <= cap of the output). */
+typedef struct {
+  double rel_tol;
+  int32_t chi_max;
+  int32_t fit_sweeps;   /* qtt_apply_mpo only: variational fitting sweeps after the
+                           zip-up (Sec. 2.2), 0..64; other calls ignore it */
+} qtt_trunc;
+
+/* Options of the variational linear solve (Sec. 2.1.4, Eq. LSE). */
+typedef struct {
+  double tol;               /* stop when ||Ax-b||/||b|| <= tol (FP64)             */
+  int32_t max_sweeps;       /* full sweeps (left-to-right + right-to-left)        */
+  int32_t max_local_iters;  /* CG iterations per local problem                    */
+  double local_tol;         /* relative residual target of each local problem     */
+  int32_t contract_dt;      /* qtt_dtype of the local matrix-vector products      */
+} qtt_solve_opts;
+
+typedef struct {
+  int32_t sweeps;           /* sweeps performed                                   */
+  int32_t local_iters;      /* total CG iterations                                */
+  double residual;          /* final ||Ax-b||/||b|| (FP64)                        */
+  double residual0;         /* initial ||Ax0-b||/||b||                            */
+} qtt_solve_info;
+
+/* ---- context ------------------------------------------------------------ */
+
+typedef struct qtt_ctx qtt_ctx;
+
+/* Create a context on HIP device `device`. The context owns only its scratch
+ * workspace (grown on demand, freed by qtt_destroy). */
+int qtt_create(int device, qtt_ctx** out);
+void qtt_destroy(qtt_ctx* ctx);
+const char* qtt_last_error(const qtt_ctx* ctx);
+
+/* ---- TT algebra (Sec. 2.1) -------------------------------------------------
+ * Every operation takes `n` independent problems (arrays of n descriptors) and
+ * runs them together, site by site. All problems of one call share L, d and the
+ * capacities. */
+
+/* y_i = round(M_i x_i): MPO times MPS (Sec. 2.1.2, mat-vec with fused bond) by a
+ * left-to-right zip-up that truncates each site as it is formed, a right-to-left
+ * truncated-SVD sweep (Sec. 2, TT-rounding) that fixes the bonds, and
+ * tr->fit_sweeps single-site variational fitting sweeps at those bonds (Sec. 2.2,
+ * the variational mat-vec of Table 1): each site becomes the projection of M x
+ * onto the orthonormal frame of the other cores, so ||y - M x|| decreases.
+ * y is left right-canonical (cores 1..L-1 right-orthonormal). x_i and y_i must
+ * not alias. contract_dt selects the MFMA type of the site contractions. */
+int qtt_apply_mpo(qtt_ctx* ctx, int n, const qtt_mpo* M, const qtt_mps* x, qtt_mps* y,
+                  const qtt_trunc* tr, int contract_dt, void* stream);
+
+/* In-place TT-rounding (Sec. 2: regular truncation): left-to-right Householder QR
+ * sweep, then right-to-left truncated SVD (one-sided Jacobi) sweep, FP64.
+ * The result is right-canonical. */
+int qtt_round(qtt_ctx* ctx, int n, qtt_mps* x, const qtt_trunc* tr, void* stream);
+
+/* z_i = round(a_i x_i + b_i y_i) (Sec. 2.1.1: direct sum, bond chi_a + chi_b, then
+ * rounding). a, b are HOST arrays of n doubles. z may alias neither x nor y. */
+int qtt_add(qtt_ctx* ctx, int n, const double* a, const qtt_mps* x, const double* b,
+            const qtt_mps* y, qtt_mps* z, const qtt_trunc* tr, void* stream);
+
+/* out[i] = <x_i, y_i> in FP64 (left environments). `out` is a HOST array of n
+ * doubles; the stream is synchronised. */
+int qtt_dot(qtt_ctx* ctx, int n, const qtt_mps* x, const qtt_mps* y, double* out, void* stream);
+
+/* out[i] = <x_i, A_i y_i> in FP64. HOST out; synchronises. */
+int qtt_dot_mpo(qtt_ctx* ctx, int n, const qtt_mps* x, const qtt_mpo* A, const qtt_mps* y,
+                double* out, void* stream);
+
+/* Diagonal scaling by a bond-1 MPO: y_i = D_i x_i where every core of D_i is a
+ * 2x2 matrix (w = 1). Exact (no truncation, bonds unchanged). */
+int qtt_apply_local(qtt_ctx* ctx, int n, const qtt_mpo* D, const qtt_mps* x, qtt_mps* y, void* stream);
+
+/* Single-site variational (ALS / one-site DMRG) solve of A x = b (Sec. 2.1.4,
+ * Eq. LSE and its cost function; local problems by CG with the fast matvec of
+ * App. G). A must be symmetric positive definite. On entry x holds the initial
+ * guess (its bond structure is kept: single-site updates cannot grow bonds); on
+ * exit the solution, right-canonical. info (HOST, n entries, may be NULL)
+ * receives sweeps, CG iterations and FP64 residuals. Returns QTT_ENOTCONVERGED
+ * if some problem stopped at max_sweeps above tol (x then holds its best iterate). */
+int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qtt_mps* b, qtt_mps* x,
+                      const qtt_solve_opts* opts, qtt_solve_info* info, void* stream);
+
+/* ---- fractional step (Sec. 3.3) ------------------------------------------- */
+
+/* Operators of the cylinder problem, built once per grid (Sec. 3.2.3, App. A),
+ * all in the interleaved order of a 2^n x 2^n O-grid (L = 2n cores).
+ * Velocity operators carry Dirichlet rows (wall, far field) whose values enter
+ * through the boundary-correction vectors (Sec. 3.1, ghost points); pressure
+ * operators use p_{-1,j} = p_{0,j} at the wall and p = 0 at the far field. */
+typedef struct {
+  qtt_mpo Dx, Dz;           /* curvilinear first derivatives (velocity BCs)      */
+  qtt_mpo Dxp, Dzp;         /* pressure gradient (pressure BCs)                  */
+  qtt_mpo Wx, Wz;           /* -|J| d/dx, -|J| d/dz (J-weighted divergence)      */
+  qtt_mpo Hs;               /* |J|^(1/2) (I - dt/Re Lap) |J|^(-1/2) on velocity (SPD) */
+  qtt_mpo P;                /* -|J| Lap with pressure BCs (SPD)                  */
+  qtt_mpo Jh, Jmh;          /* |J|^(1/2), |J|^(-1/2) as bond-1 diagonal MPOs     */
+  qtt_mps bx_u, bz_u;       /* boundary corrections of Dx, Dz for u              */
+  qtt_mps bx_v, bz_v;       /* ... for v                                         */
+  qtt_mps bL_u, bL_v;       /* (dt/Re) x boundary corrections of Lap for u, v    */
+  qtt_mps bW;               /* boundary correction of Wx u + Wz v                */
+} qtt_flow_ops;
+
+typedef struct {
+  qtt_mps u, v, p;          /* current fields (right-canonical)                  */
+} qtt_flow_state;
+
+typedef struct {
+  double dt;                /* time step                                          */
+  qtt_trunc trunc;          /* truncation of every TT operation of the step       */
+  int32_t contract_dt;      /* qtt_dtype of applies, Hadamards and local matvecs  */
+  qtt_solve_opts helmholtz; /* options of the two predictor solves                */
+  qtt_solve_opts poisson;   /* options of the pressure solve                      */
+} qtt_step_opts;
+
+typedef struct {
+  qtt_solve_info helm_u, helm_v, poisson;
+} qtt_step_info;
+
+/* One Chorin fractional step (Sec. 3.3): explicit convection (Hadamard products of
+ * v with its curvilinear gradients), implicit viscous predictor (Eq.
+ * intermediate_vel_eq, solved variationally in the symmetric form
+ * |J|^(1/2)(I - dt/Re Lap)|J|^(-1/2)), J-weighted pressure Poisson solve (Sec. 3.3),
+ * projection v = v* - dt grad p. state->p is the initial guess of the pressure
+ * solve and receives the new pressure. The solves read their FP64 residual on
+ * the host once per sweep, so the call synchronises its stream. A solve that
+ * stops at its bond-limited floor above tol is not an error here: info (HOST,
+ * may be NULL) receives the sweeps, CG iterations and residuals of the three solves.
+ * All seven boundary vectors must share one capacity. */
+int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_flow_state* state,
+                        const qtt_step_opts* opts, qtt_step_info* info, void* stream);
+
+/* ---- host-side operator construction (setup, FP64, no GPU) ----------------
+ * Builds, on the host, the TT cores of the operators and boundary vectors of a
+ * 2^n x 2^n O-grid around a unit cylinder (App. E: r_i = 0.5 (2 r_out)^((i+1)/(N+1)),
+ * metrics by central differences, App. A), encodes each coefficient field by
+ * TT-SVD and assembles sum_o diag(c_o) Shift_o, then rounds the MPO, dropping
+ * singular values below 1e-14 of the largest (Sec. 3.2.3).
+ *
+ * `which` selects the object (QTT_OP_* below). For an MPO, cores are written to
+ * `out` (HOST, wcap*4*wcap*L doubles) and bonds to `bond_out` (HOST int32[L+1]);
+ * for a vector (QTT_VEC_*), cores go to `out` with slot cap*2*cap and bonds to
+ * bond_out. `wcap`/`cap` is the slot size the caller allocated;
+ * QTT_ECAPACITY if the object needs more. Call with out == NULL to query the
+ * needed capacity in *need. Parameters: n (cores per axis), r_out, Re, dt,
+ * alpha (wall rotation rate, Eq. rot_bc), u_inf (far-field velocity). */
+enum {
+  QTT_OP_DX = 0, QTT_OP_DZ, QTT_OP_DXP, QTT_OP_DZP, QTT_OP_WX, QTT_OP_WZ,
+  QTT_OP_HS, QTT_OP_P, QTT_OP_JH, QTT_OP_JMH, QTT_OP_LAP,
+  QTT_VEC_BX_U = 100, QTT_VEC_BZ_U, QTT_VEC_BX_V, QTT_VEC_BZ_V, QTT_VEC_BL_U,
+  QTT_VEC_BL_V, QTT_VEC_BW, QTT_VEC_ABSJ
+};
+typedef struct {
+  int32_t n;       /* cores per axis; L = 2n, grid 2^n x 2^n */
+  double r_out;    /* outer radius (cylinder diameter 1)      */
+  double Re, dt;   /* Reynolds number, time step              */
+  double alpha;    /* wall rotation rate                       */
+  double u_inf;    /* far-field velocity (x direction)         */
+} qtt_cylinder;
+
+int qtt_build_host(const qtt_cylinder* cyl, int which, int32_t cap, double* out,
+                   int32_t* bond_out, int32_t* need);
+
+/* Host TT-SVD of a dense vector of d^L doubles (App. D; same truncation rule as
+ * qtt_trunc), used to encode initial fields. Writes cores into slots of
+ * cap*d*cap doubles (HOST) and bonds to bond_out (HOST int32[L+1]). */
+int qtt_tt_svd_host(const double* dense, int32_t L, int32_t d, const qtt_trunc* tr,
+                    int32_t cap, double* out, int32_t* bond_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QTT_H */

@@ -1,0 +1,292 @@
+// Device building blocks shared by the kernel translation units: the MFMA
+// block-GEMM tile, wavefront reductions, one-sided Jacobi and Householder QR
+// for one workgroup. Everything here has internal linkage.
+#pragma once
+#include "internal.h"
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int TILE = 64;          // output tile of the block GEMM (64 x 64, 256 threads)
+constexpr int FACT_THREADS = 1024; // threads of the one-workgroup factorisation kernels
+constexpr int MAXN = 512;         // max columns handled by the factorisation kernels
+
+
+__host__ __device__ inline size_t align64(size_t x) { return (x + 63) & ~size_t(63); }
+
+// ---------------------------------------------------------------------------
+// block GEMM tile on MFMA
+//   C(m, n) = alpha * sum_{k0 <= k < k1} A(m, k) B(k, n) + beta * C(m, n)
+//   for m0 <= m < m0 + 64, n0 <= n < n0 + 64 (clipped to M, N).
+// Operands are strided views: A(m, k) = A.p[m*A.rs + k*A.cs]. Values outside the
+// bounds read as zero. MODE 0: FP64 MFMA 16x16x4 (FP64 accumulate); MODE 1: FP32
+// MFMA 16x16x4; MODE 2: BF16 MFMA 16x16x32 (FP32 accumulate).
+// Operand lane layout (all three): lane l holds A[l%16][k-group l/16] and
+// B[k-group l/16][l%16]. Result layout: FP64 D[l/16 + 4v][l%16], FP32/BF16
+// D[4(l/16) + v][l%16].
+// ---------------------------------------------------------------------------
+struct View { const double* p; long rs, cs; };
+
+template <int MODE> struct Cfg;
+template <> struct Cfg<0> { using T = double; using Acc = v4d; static constexpr int BK = 16; static constexpr int PAD = 1; };
+template <> struct Cfg<1> { using T = float;  using Acc = v4f; static constexpr int BK = 16; static constexpr int PAD = 1; };
+template <> struct Cfg<2> { using T = __bf16; using Acc = v4f; static constexpr int BK = 32; static constexpr int PAD = 8; };
+
+template <int MODE>
+__device__ __forceinline__ typename Cfg<MODE>::T to_t(double v) {
+  if constexpr (MODE == 2) return (__bf16)(float)v;
+  else return (typename Cfg<MODE>::T)v;
+}
+
+template <int MODE>
+__device__ void gemm_tile(int M, int N, int k0, int k1, View A, View B, double* C, long crs, long ccs,
+                          double alpha, double beta, int m0, int n0) {
+  using T = typename Cfg<MODE>::T;
+  using Acc = typename Cfg<MODE>::Acc;
+  constexpr int BK = Cfg<MODE>::BK;
+  constexpr int PAD = Cfg<MODE>::PAD;
+  __shared__ __attribute__((aligned(16))) T As[TILE][BK + PAD];
+  __shared__ __attribute__((aligned(16))) T Bs[TILE][BK + PAD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  Acc acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+
+  for (int kb = k0; kb < k1; kb += BK) {
+    for (int e = tid; e < TILE * BK; e += 256) {
+      int i, kk;
+      if (A.cs == 1) { i = e / BK; kk = e % BK; } else { i = e % TILE; kk = e / TILE; }
+      const int gm = m0 + i, gk = kb + kk;
+      const double v = (gm < M && gk < k1) ? A.p[(long)gm * A.rs + (long)gk * A.cs] : 0.0;
+      As[i][kk] = to_t<MODE>(v);
+    }
+    for (int e = tid; e < TILE * BK; e += 256) {
+      int j, kk;
+      if (B.cs == 1) { j = e % TILE; kk = e / TILE; } else { kk = e % BK; j = e / BK; }
+      const int gn = n0 + j, gk = kb + kk;
+      const double v = (gn < N && gk < k1) ? B.p[(long)gk * B.rs + (long)gn * B.cs] : 0.0;
+      Bs[j][kk] = to_t<MODE>(v);
+    }
+    __syncthreads();
+    if constexpr (MODE == 0) {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        const double a0 = As[wm + li][kk + lk], a1 = As[wm + 16 + li][kk + lk];
+        const double b0 = Bs[wn + li][kk + lk], b1 = Bs[wn + 16 + li][kk + lk];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      }
+    } else if constexpr (MODE == 1) {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        const float a0 = As[wm + li][kk + lk], a1 = As[wm + 16 + li][kk + lk];
+        const float b0 = Bs[wn + li][kk + lk], b1 = Bs[wn + 16 + li][kk + lk];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+      }
+    } else {
+      const v8bf a0 = *reinterpret_cast<const v8bf*>(&As[wm + li][8 * lk]);
+      const v8bf a1 = *reinterpret_cast<const v8bf*>(&As[wm + 16 + li][8 * lk]);
+      const v8bf b0 = *reinterpret_cast<const v8bf*>(&Bs[wn + li][8 * lk]);
+      const v8bf b1 = *reinterpret_cast<const v8bf*>(&Bs[wn + 16 + li][8 * lk]);
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  for (int bi = 0; bi < 2; ++bi)
+    for (int bj = 0; bj < 2; ++bj)
+      for (int v = 0; v < 4; ++v) {
+        const int r = (MODE == 0) ? (lk + 4 * v) : (4 * lk + v);
+        const int gm = m0 + wm + bi * 16 + r, gn = n0 + wn + bj * 16 + li;
+        if (gm < M && gn < N) {
+          double val = alpha * (double)acc[bi][bj][v];
+          double* cp = C + (long)gm * crs + (long)gn * ccs;
+          if (beta != 0.0) val += beta * (*cp);
+          *cp = val;
+        }
+      }
+}
+
+#define DISPATCH_MODE(mode, KERNEL, ...)                        \
+  do {                                                          \
+    if ((mode) == 0) KERNEL<0>(__VA_ARGS__);                    \
+    else if ((mode) == 1) KERNEL<1>(__VA_ARGS__);               \
+    else KERNEL<2>(__VA_ARGS__);                                \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// wavefront / workgroup helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return __shfl(v, 0, 64);   // every lane takes lane 0's value: identical decisions
+}
+
+// One-sided Jacobi (Hestenes 1958) on the n columns of X (m rows; column j at
+// X + j*ldx). Rotations are accumulated into V (n x n, column j at V + j*ldv)
+// when V is not null. Parallel cyclic (round-robin) ordering: each round
+// rotates n/2 disjoint column pairs, one pair per wavefront at a time. Stops
+// after a sweep without rotations (|x_p.x_q| <= tol sqrt(|x_p|^2 |x_q|^2)).
+__device__ void jacobi_cols(double* X, int m, int ldx, int n, double* V, int ldv, int* flag) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int ne = n + (n & 1);
+  const double tol = 4.0e-16 * sqrt((double)(m > 1 ? m : 1));
+  if (n < 2) return;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (threadIdx.x == 0) *flag = 0;
+    __syncthreads();
+    for (int r = 0; r < ne - 1; ++r) {
+      for (int pi = wave; pi < ne / 2; pi += nw) {
+        int p, q;
+        if (pi == 0) { p = ne - 1; q = r; }
+        else { p = (r + pi) % (ne - 1); q = (r - pi + ne - 1) % (ne - 1); }
+        if (p >= n || q >= n) continue;
+        double* xp = X + (long)p * ldx;
+        double* xq = X + (long)q * ldx;
+        double a = 0, b = 0, c = 0;
+        for (int i = lane; i < m; i += 64) {
+          const double u = xp[i], w = xq[i];
+          a += u * u; b += w * w; c += u * w;
+        }
+        a = wave_sum(a); b = wave_sum(b); c = wave_sum(c);
+        if (!(a > 1e-300) || !(b > 1e-300)) continue;
+        if (fabs(c) <= tol * sqrt(a) * sqrt(b)) continue;
+        const double zeta = (b - a) / (2.0 * c);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+        for (int i = lane; i < m; i += 64) {
+          const double u = xp[i], w = xq[i];
+          xp[i] = cs * u - sn * w;
+          xq[i] = sn * u + cs * w;
+        }
+        if (V) {
+          double* vp = V + (long)p * ldv;
+          double* vq = V + (long)q * ldv;
+          for (int i = lane; i < n; i += 64) {
+            const double u = vp[i], w = vq[i];
+            vp[i] = cs * u - sn * w;
+            vq[i] = sn * u + cs * w;
+          }
+        }
+        if (lane == 0) *flag = 1;
+      }
+      __syncthreads();
+    }
+    const int f = *flag;
+    __syncthreads();
+    if (f == 0) break;
+  }
+}
+
+// Column norms of X and the permutation sorting them in decreasing order
+// (ties by index). sig[j] = |x_j|, ord[pos] = j.
+__device__ void sorted_norms(const double* X, int m, int ldx, int n, double* sig, int* ord) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int j = wave; j < n; j += nw) {
+    double a = 0;
+    for (int i = lane; i < m; i += 64) { const double u = X[(long)j * ldx + i]; a += u * u; }
+    a = wave_sum(a);
+    if (lane == 0) sig[j] = sqrt(a);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    int pos = 0;
+    const double s = sig[j];
+    for (int i = 0; i < n; ++i) pos += (sig[i] > s) || (sig[i] == s && i < j);
+    ord[pos] = j;
+  }
+  __syncthreads();
+}
+
+// Truncation rank from sorted singular values s (via ord): smallest r whose
+// discarded tail has norm <= delta, capped at cap, at least 1. Single thread.
+__device__ int trunc_rank(const double* sig, const int* ord, int n, double delta, int cap) {
+  double tail = 0.0;
+  int r = n;
+  for (int q = n - 1; q >= 0; --q) {
+    const double s = sig[ord[q]];
+    if (sqrt(tail + s * s) <= delta) { tail += s * s; r = q; }
+    else break;
+  }
+  if (r > cap) r = cap;
+  if (r < 1) r = 1;
+  return r;
+}
+
+// Householder QR of X (m x n, column-major, ld m) in place: on exit the
+// reflector vectors v_j occupy X[j.., j], R's strict upper part X[i, c] (i < c),
+// R's diagonal in rdiag[j] and the reflector factors in tau[j]. r = min(m, n).
+__device__ void householder(double* X, int m, int n, double* rdiag, double* tau) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int r = m < n ? m : n;
+  for (int j = 0; j < r; ++j) {
+    double* xj = X + (long)j * m;
+    if (wave == 0) {
+      double s = 0;
+      for (int i = j + lane; i < m; i += 64) s += xj[i] * xj[i];
+      s = wave_sum(s);
+      const double x0 = xj[j];
+      if (lane == 0) {
+        if (s == 0.0) { rdiag[j] = 0.0; tau[j] = 0.0; }
+        else {
+          const double nrm = sqrt(s);
+          const double alpha = x0 >= 0 ? -nrm : nrm;
+          const double v0 = x0 - alpha;
+          const double vtv = s - x0 * x0 + v0 * v0;
+          rdiag[j] = alpha;
+          tau[j] = vtv > 0 ? 2.0 / vtv : 0.0;
+          xj[j] = v0;
+        }
+      }
+    }
+    __syncthreads();
+    const double tj = tau[j];
+    if (tj != 0.0) {
+      for (int c = j + 1 + wave; c < n; c += nw) {
+        double* xc = X + (long)c * m;
+        double w = 0;
+        for (int i = j + lane; i < m; i += 64) w += xj[i] * xc[i];
+        w = wave_sum(w) * tj;
+        for (int i = j + lane; i < m; i += 64) xc[i] -= w * xj[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Thin Q (m x r, column-major ld m) from the reflectors left in X by householder().
+__device__ void householder_q(const double* X, int m, int n, const double* tau, double* Q) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int r = m < n ? m : n;
+  for (int e = threadIdx.x; e < m * r; e += blockDim.x) Q[e] = ((e % m) == (e / m)) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int j = r - 1; j >= 0; --j) {
+    const double tj = tau[j];
+    const double* v = X + (long)j * m;
+    if (tj != 0.0) {
+      for (int c = j + wave; c < r; c += nw) {
+        double* qc = Q + (long)c * m;
+        double w = 0;
+        for (int i = j + lane; i < m; i += 64) w += v[i] * qc[i];
+        w = wave_sum(w) * tj;
+        for (int i = j + lane; i < m; i += 64) qc[i] -= w * v[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace

@@ -1,0 +1,619 @@
+// HIP kernels for gfx950 (MI355X): site contractions on MFMA, one-sided Jacobi
+// SVD and Householder QR sweeps in FP64, and the small element-wise kernels of
+// the tensor-train algebra (Sec. 2.1 of arxiv 2507.05222).
+//
+// Every kernel works on a batch of independent chains (Batch, up to QTT_BMAX),
+// one site at a time. Bond dimensions are read from device memory, so a whole
+// operation is enqueued without host synchronisation; grids are sized for the
+// slot capacities and tiles beyond the actual bonds exit at once.
+#include "internal.h"
+
+#include <cstdio>
+
+#include "device_common.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// zip-up MPO x MPS with on-the-fly truncation
+// carry C[a'][bw][c]  (rows (a', bw) with stride capx)   : chi'_k x w_k x chi_k
+// T1[a'][bw][s][c]    (rows (a', bw) with stride 2 capx) : carry . X_k
+// Theta[a'][r'][bw'][c] (row (a', r') of length w_{k+1} capx) : sum_{bw, s} M_k T1
+// ---------------------------------------------------------------------------
+__device__ inline size_t slot(int cap, int d) { return (size_t)cap * d * cap; }
+
+__global__ void k_zip_init(Batch b, WsLayout wl) {
+  if (blockIdx.x >= b.n) return;
+  Chain& c = b.c[blockIdx.x];
+  if (threadIdx.x == 0) {
+    c.ws[wl.carry] = 1.0;
+    c.yb[0] = 1;
+  }
+  if (threadIdx.x < SC_COUNT) c.ws[wl.scal + threadIdx.x] = 0.0;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_zip_t1(Batch b, Geo g, WsLayout wl) {
+  if (blockIdx.z >= b.n) return;
+  Chain& c = b.c[blockIdx.z];
+  const int k = g.k;
+  const int M = c.yb[k] * c.mb[k], K = c.xb[k], N = 2 * g.capx;
+  const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
+  if (m0 >= M) return;
+  View A{c.ws + wl.carry, g.capx, 1};
+  View B{c.x + (long)k * slot(g.capx, 2), 2 * g.capx, 1};
+  gemm_tile<MODE>(M, N, 0, K, A, B, c.ws + wl.t1, 2 * g.capx, 1, 1.0, 0.0, m0, n0);
+}
+
+__global__ void k_mpo_transpose(Batch b, Geo g, WsLayout wl) {
+  const int k = blockIdx.x;
+  if (blockIdx.y >= b.n) return;
+  Chain& c = b.c[blockIdx.y];
+  const int w = c.mb[k], w2 = c.mb[k + 1];
+  const double* Mk = c.m + (long)k * slot(g.wcap, 4);
+  double* T = c.ws + wl.mt + (size_t)k * (2 * g.W) * (2 * g.W);
+  // T[(r' w2 + bw')][(bw 2 + s)] = M_k[bw][r'][s][bw'], row length 2w
+  for (int e = threadIdx.x; e < 4 * w * w2; e += blockDim.x) {
+    const int i = e / (2 * w), kk = e % (2 * w);
+    const int rp = i / w2, bwp = i % w2, bw = kk / 2, s = kk % 2;
+    T[e] = Mk[(long)bw * 4 * g.wcap + rp * 2 * g.wcap + s * g.wcap + bwp];
+  }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_zip_t2(Batch b, Geo g, WsLayout wl) {
+  const int ci = blockIdx.z / g.capy, ap = blockIdx.z % g.capy;
+  if (ci >= b.n) return;
+  Chain& c = b.c[ci];
+  const int k = g.k;
+  if (ap >= c.yb[k]) return;
+  const int w = c.mb[k], w2 = c.mb[k + 1];
+  const int M = 2 * w2, K = 2 * w, N = g.capx;
+  const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
+  if (m0 >= M) return;
+  View A{c.ws + wl.mt + (size_t)k * (2 * g.W) * (2 * g.W), 2 * w, 1};
+  View B{c.ws + wl.t1 + (long)ap * w * 2 * g.capx, g.capx, 1};
+  gemm_tile<MODE>(M, N, 0, K, A, B, c.ws + wl.theta + (long)ap * 2 * w2 * g.capx, g.capx, 1, 1.0, 0.0,
+                  m0, n0);
+}
+
+// Gram G = Theta Theta^T (FP64), split over K into wl.splits partial products.
+__global__ void __launch_bounds__(256) k_zip_gram(Batch b, Geo g, WsLayout wl) {
+  const int ci = blockIdx.z / wl.splits, sp = blockIdx.z % wl.splits;
+  if (ci >= b.n) return;
+  Chain& c = b.c[ci];
+  const int k = g.k;
+  const int M = 2 * c.yb[k], w2 = c.mb[k + 1];
+  const int K = w2 * g.capx;
+  const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
+  if (m0 >= M || n0 >= M) return;
+  int chunk = (K + wl.splits - 1) / wl.splits;
+  chunk = (chunk + 15) & ~15;
+  const int k0 = sp * chunk;
+  const int k1 = (k0 + chunk < K) ? k0 + chunk : K;
+  const double* th = c.ws + wl.theta;
+  View A{th, (long)K, 1};
+  View B{th, 1, (long)K};
+  const int ld = 2 * g.capy;
+  gemm_tile<0>(M, M, k0, k1 > k0 ? k1 : k0, A, B, c.ws + wl.gpart + (size_t)sp * ld * ld, ld, 1, 1.0, 0.0,
+               m0, n0);
+}
+
+// Truncated eigen-decomposition of G (= left singular vectors of Theta): one
+// workgroup per chain. Writes U (first r eigenvectors, decreasing eigenvalue)
+// as core k of y and sets y.bond[k+1] = r.
+__global__ void __launch_bounds__(FACT_THREADS) k_zip_factor(Batch b, Geo g, WsLayout wl) {
+  extern __shared__ double smem[];
+  __shared__ double sig[MAXN];
+  __shared__ int ord[MAXN];
+  __shared__ int flag, rank;
+  if (blockIdx.x >= b.n) return;
+  Chain& c = b.c[blockIdx.x];
+  const int k = g.k;
+  const int m = 2 * c.yb[k];
+  const int ldg = 2 * g.capy;
+  const bool in_lds = (size_t)m * m * sizeof(double) <= (size_t)g.lds;
+  double* G = in_lds ? smem : (c.ws + wl.gpart);
+  const int ld = in_lds ? m : ldg;
+  // G is symmetric: column j is read from row j of the partial products, so in
+  // the global-memory path each thread reads and writes the same element.
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    const int i = e % m, j = e / m;
+    double s = 0;
+    for (int sp = 0; sp < wl.splits; ++sp) s += c.ws[wl.gpart + (size_t)sp * ldg * ldg + (size_t)j * ldg + i];
+    G[(long)j * ld + i] = s;
+  }
+  __syncthreads();
+  jacobi_cols(G, m, ld, m, nullptr, 0, &flag);
+  sorted_norms(G, m, ld, m, sig, ord);
+  if (threadIdx.x == 0) {
+    const double lam0 = sig[ord[0]];
+    const double tau = 0.01 * g.tol / sqrt((double)(g.L > 1 ? g.L - 1 : 1));
+    const double thr = lam0 * tau * tau;
+    int cap = g.chi_max < g.capy ? g.chi_max : g.capy;
+    int r = 0;
+    for (int q = 0; q < m; ++q) if (sig[ord[q]] > thr && sig[ord[q]] > 1e-300) r = q + 1;
+    if (r > cap) r = cap;
+    if (r < 1) r = 1;
+    double disc = 0;
+    for (int q = r; q < m; ++q) disc += sig[ord[q]];
+    c.ws[wl.scal + SC_TRUNC2] += disc;
+    rank = r;
+    c.yb[k + 1] = r;
+  }
+  __syncthreads();
+  const int r = rank;
+  double* Y = c.y + (long)k * slot(g.capy, 2);
+  const int S = g.capy * 2 * g.capy;
+  for (int e = threadIdx.x; e < S; e += blockDim.x) {
+    const int row = e / g.capy, n = e % g.capy;     // row = a' * 2 + r'
+    double v = 0.0;
+    if (row < m && n < r) {
+      const int j = ord[n];
+      const double lam = sig[j];
+      v = lam > 0 ? G[(long)j * ld + row] / lam : 0.0;
+    }
+    Y[e] = v;
+  }
+}
+
+// carry' = U^T Theta (FP64 projection onto the kept left singular vectors)
+__global__ void __launch_bounds__(256) k_zip_carry(Batch b, Geo g, WsLayout wl) {
+  if (blockIdx.z >= b.n) return;
+  Chain& c = b.c[blockIdx.z];
+  const int k = g.k;
+  const int r = c.yb[k + 1], m = 2 * c.yb[k], w2 = c.mb[k + 1];
+  const int N = w2 * g.capx;
+  const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
+  if (m0 >= r || n0 >= N) return;
+  View A{c.y + (long)k * slot(g.capy, 2), 1, g.capy};
+  View B{c.ws + wl.theta, (long)N, 1};
+  gemm_tile<0>(r, N, 0, m, A, B, c.ws + wl.carry, N, 1, 1.0, 0.0, m0, n0);
+}
+
+// last site: Theta is (2 chi') x 1; it is the last core.
+__global__ void k_zip_last(Batch b, Geo g, WsLayout wl) {
+  if (blockIdx.x >= b.n) return;
+  Chain& c = b.c[blockIdx.x];
+  const int k = g.L - 1;
+  const int chi = c.yb[k];
+  double* Y = c.y + (long)k * slot(g.capy, 2);
+  const double* th = c.ws + wl.theta;
+  const int S = g.capy * 2 * g.capy;
+  for (int e = threadIdx.x; e < S; e += blockDim.x) {
+    const int a = e / (2 * g.capy), s = (e / g.capy) % 2, n = e % g.capy;
+    Y[e] = (a < chi && n == 0) ? th[(long)a * 2 * g.capx + s * g.capx] : 0.0;
+  }
+  if (threadIdx.x == 0) c.yb[g.L] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// right-to-left truncated SVD sweep (TT-rounding of a left-orthogonal train)
+// ---------------------------------------------------------------------------
+// Site k: Y_k (b_k x 2 b_{k+1}) = V S W^T by one-sided Jacobi on X = Y_k^T;
+// new core k = first r rows of W^T (right-orthonormal); tmp <- Y_{k-1} (V S)[:, :r].
+__global__ void __launch_bounds__(FACT_THREADS) k_rl_svd(Batch b, Geo g, WsLayout wl, int from_tmp) {
+  extern __shared__ double smem[];
+  __shared__ double sig[MAXN];
+  __shared__ int ord[MAXN];
+  __shared__ int flag, rank;
+  if (blockIdx.x >= b.n) return;
+  Chain& c = b.c[blockIdx.x];
+  const int k = g.k, cap = g.capy;
+  const int nb = c.yb[k], mb = c.yb[k + 1];
+  const int m = 2 * mb;
+  const size_t need = ((size_t)m * nb + (size_t)nb * nb) * sizeof(double);
+  const bool in_lds = need <= (size_t)g.lds;
+  double* X = in_lds ? smem : (c.ws + wl.gpart);
+  double* V = X + (size_t)m * nb;
+  const double* src = from_tmp ? (c.ws + wl.tmpA) : (c.y + (long)k * slot(cap, 2));
+  for (int e = threadIdx.x; e < m * nb; e += blockDim.x) {
+    const int a = e / m, rho = e % m, s = rho / mb, bb = rho % mb;
+    X[e] = src[(long)a * 2 * cap + s * cap + bb];
+  }
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) V[e] = ((e % nb) == (e / nb)) ? 1.0 : 0.0;
+  __syncthreads();
+  jacobi_cols(X, m, m, nb, V, nb, &flag);
+  sorted_norms(X, m, m, nb, sig, ord);
+  double* scal = c.ws + wl.scal;
+  if (threadIdx.x == 0) {
+    if (k == g.L - 1) {
+      double s2 = 0;
+      for (int q = 0; q < nb; ++q) s2 += sig[q] * sig[q];
+      scal[SC_NORM2] = s2;
+    }
+    const double delta = g.tol / sqrt((double)(g.L > 1 ? g.L - 1 : 1)) * sqrt(scal[SC_NORM2]);
+    int capr = g.chi_max < cap ? g.chi_max : cap;
+    if (capr > m) capr = m;                       // rank of a (2 b_{k+1}) x b_k matrix
+    int r = trunc_rank(sig, ord, nb, delta, capr);
+    // singular values at round-off level carry no information (and no orthonormal
+    // direction): drop them
+    const double floor_ = 1e-14 * sig[ord[0]];
+    while (r > 1 && !(sig[ord[r - 1]] > floor_)) --r;
+    double disc = 0;
+    for (int q = r; q < nb; ++q) disc += sig[ord[q]] * sig[ord[q]];
+    scal[SC_TRUNC2] += disc;
+    rank = r;
+  }
+  __syncthreads();
+  const int r = rank;
+  // new right-orthonormal core k
+  double* Yk = c.y + (long)k * slot(cap, 2);
+  const int S = cap * 2 * cap;
+  for (int e = threadIdx.x; e < S; e += blockDim.x) {
+    const int n = e / (2 * cap), s = (e / cap) % 2, bb = e % cap;
+    double v = 0.0;
+    if (n < r && bb < mb) {
+      const int j = ord[n];
+      v = sig[j] > 0 ? X[(long)j * m + s * mb + bb] / sig[j] : 0.0;
+    }
+    Yk[e] = v;
+  }
+  // tmp <- Y_{k-1} (V S)[:, :r]
+  const int nprev = c.yb[k - 1];
+  const double* Yp = c.y + (long)(k - 1) * slot(cap, 2);
+  double* T = c.ws + wl.tmpA;
+  __syncthreads();
+  for (int e = threadIdx.x; e < S; e += blockDim.x) {
+    const int a0 = e / (2 * cap), s = (e / cap) % 2, n = e % cap;
+    double v = 0.0;
+    if (a0 < nprev && n < r) {
+      const int j = ord[n];
+      const double* yrow = Yp + (long)a0 * 2 * cap + s * cap;
+      const double* vcol = V + (long)j * nb;
+      for (int a = 0; a < nb; ++a) v += yrow[a] * vcol[a];
+      v *= sig[j];
+    }
+    T[e] = v;
+  }
+  if (threadIdx.x == 0) c.yb[k] = r;
+}
+
+__global__ void k_tmp_to_slot(Batch b, Geo g, WsLayout wl, int site) {
+  if (blockIdx.x >= b.n) return;
+  Chain& c = b.c[blockIdx.x];
+  double* Y = c.y + (long)site * slot(g.capy, 2);
+  const double* T = c.ws + wl.tmpA;
+  const int S = g.capy * 2 * g.capy;
+  for (int e = threadIdx.x; e < S; e += blockDim.x) Y[e] = T[e];
+}
+
+// ---------------------------------------------------------------------------
+// left-to-right Householder QR sweep (orthogonalisation, no truncation)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(FACT_THREADS) k_lr_qr(Batch b, Geo g, WsLayout wl, int from_tmp) {
+  extern __shared__ double smem[];
+  __shared__ double rdiag[MAXN], tau[MAXN];
+  __shared__ int rk;
+  if (blockIdx.x >= b.n) return;
+  Chain& c = b.c[blockIdx.x];
+  const int k = g.k, cap = g.capy;
+  const int m = 2 * c.yb[k], n = c.yb[k + 1];
+  const int r = m < n ? m : n;
+  const size_t need = ((size_t)m * n + (size_t)m * r) * sizeof(double);
+  const bool in_lds = need <= (size_t)g.lds;
+  double* X = in_lds ? smem : (c.ws + wl.gpart);
+  double* Q = X + (size_t)m * n;
+  const double* src = from_tmp ? (c.ws + wl.tmpA) : (c.y + (long)k * slot(cap, 2));
+  for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
+    const int j = e / m, i = e % m;     // i = a*2 + s
+    X[e] = src[(long)i * cap + j];
+  }
+  if (threadIdx.x == 0) rk = r;
+  __syncthreads();
+  householder(X, m, n, rdiag, tau);
+  householder_q(X, m, n, tau, Q);
+  double* Yk = c.y + (long)k * slot(cap, 2);
+  const int S = cap * 2 * cap;
+  for (int e = threadIdx.x; e < S; e += blockDim.x) {
+    const int i = e / cap, j = e % cap;   // i = a*2+s
+    Yk[e] = (i < m && j < r) ? Q[(long)j * m + i] : 0.0;
+  }
+  // tmp <- R Y_{k+1}
+  const int n2 = c.yb[k + 2];
+  const double* Yn = c.y + (long)(k + 1) * slot(cap, 2);
+  double* T = c.ws + wl.tmpA;
+  __syncthreads();
+  for (int e = threadIdx.x; e < S; e += blockDim.x) {
+    const int j = e / (2 * cap), s = (e / cap) % 2, bb = e % cap;
+    double v = 0.0;
+    if (j < r && bb < n2) {
+      v = rdiag[j] * Yn[(long)j * 2 * cap + s * cap + bb];
+      for (int t = j + 1; t < n; ++t) v += X[(long)t * m + j] * Yn[(long)t * 2 * cap + s * cap + bb];
+    }
+    T[e] = v;
+  }
+  if (threadIdx.x == 0) c.yb[k + 1] = r;
+}
+
+// ---------------------------------------------------------------------------
+// element-wise tensor-train kernels
+// ---------------------------------------------------------------------------
+// y = alpha x (+) beta x2 (Sec. 2.1.1); weights enter through the first cores.
+__global__ void k_direct_sum(Batch b, Geo g) {
+  const int k = blockIdx.x;
+  if (blockIdx.y >= b.n) return;
+  Chain& c = b.c[blockIdx.y];
+  const int L = g.L;
+  const int xa0 = c.xb[k], xa1 = c.xb[k + 1], ya0 = c.x2b[k], ya1 = c.x2b[k + 1];
+  const int oi = (k == 0) ? 0 : xa0, oj = (k == L - 1) ? 0 : xa1;
+  const double wa = (k == 0) ? c.alpha : 1.0, wb = (k == 0) ? c.beta : 1.0;
+  const double* X = c.x + (long)k * slot(g.capx, 2);
+  const double* X2 = c.x2 + (long)k * slot(g.cap2, 2);
+  double* Y = c.y + (long)k * slot(g.capy, 2);
+  const int cy = g.capy;
+  for (int e = threadIdx.x; e < cy * 2 * cy; e += blockDim.x) {
+    const int a = e / (2 * cy), s = (e / cy) % 2, bb = e % cy;
+    double v = 0.0;
+    if (a < xa0 && bb < xa1) v = wa * X[(long)a * 2 * g.capx + s * g.capx + bb];
+    const int a2 = a - oi, b2 = bb - oj;
+    if (a2 >= 0 && a2 < ya0 && b2 >= 0 && b2 < ya1) v += wb * X2[(long)a2 * 2 * g.cap2 + s * g.cap2 + b2];
+    Y[e] = v;
+  }
+  if (threadIdx.x == 0) {
+    c.yb[k + 1] = (k == L - 1) ? 1 : xa1 + ya1;
+    if (k == 0) c.yb[0] = 1;
+  }
+}
+
+__global__ void k_copy(Batch b, Geo g) {
+  const int k = blockIdx.x;
+  if (blockIdx.y >= b.n) return;
+  Chain& c = b.c[blockIdx.y];
+  const int a0 = c.xb[k], a1 = c.xb[k + 1];
+  const double w = (k == 0) ? c.alpha : 1.0;
+  const double* X = c.x + (long)k * slot(g.capx, 2);
+  double* Y = c.y + (long)k * slot(g.capy, 2);
+  const int cy = g.capy;
+  for (int e = threadIdx.x; e < cy * 2 * cy; e += blockDim.x) {
+    const int a = e / (2 * cy), s = (e / cy) % 2, bb = e % cy;
+    Y[e] = (a < a0 && bb < a1) ? w * X[(long)a * 2 * g.capx + s * g.capx + bb] : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    c.yb[k + 1] = a1;
+    if (k == 0) c.yb[0] = 1;
+  }
+}
+
+// diagonal TT-matrix of an MPS via the copy tensor (Sec. 2.1.3); y is MPO storage, wcap = capx
+__global__ void k_diag_mpo(Batch b, Geo g) {
+  const int k = blockIdx.x;
+  if (blockIdx.y >= b.n) return;
+  Chain& c = b.c[blockIdx.y];
+  const int cx = g.capx;
+  const double* X = c.x + (long)k * slot(cx, 2);
+  double* D = c.y + (long)k * slot(cx, 4);
+  for (int e = threadIdx.x; e < cx * 4 * cx; e += blockDim.x) {
+    const int a = e / (4 * cx), o = (e / (2 * cx)) % 2, r = (e / cx) % 2, bb = e % cx;
+    D[e] = (o == r) ? X[(long)a * 2 * cx + o * cx + bb] : 0.0;
+  }
+  if (threadIdx.x == 0) {
+    c.yb[k + 1] = c.xb[k + 1];
+    if (k == 0) c.yb[0] = 1;
+  }
+}
+
+// y = D x with D a bond-1 MPO (a local 2x2 matrix per site): exact, bonds unchanged
+__global__ void k_apply_local(Batch b, Geo g) {
+  const int k = blockIdx.x;
+  if (blockIdx.y >= b.n) return;
+  Chain& c = b.c[blockIdx.y];
+  const double* Dk = c.m + (long)k * slot(g.wcap, 4);
+  const double d00 = Dk[0], d01 = Dk[g.wcap], d10 = Dk[2 * g.wcap], d11 = Dk[3 * g.wcap];
+  const int cx = g.capx;
+  const double* X = c.x + (long)k * slot(cx, 2);
+  double* Y = c.y + (long)k * slot(g.capy, 2);
+  const int a0 = c.xb[k], a1 = c.xb[k + 1], cy = g.capy;
+  for (int e = threadIdx.x; e < cy * 2 * cy; e += blockDim.x) {
+    const int a = e / (2 * cy), o = (e / cy) % 2, bb = e % cy;
+    double v = 0.0;
+    if (a < a0 && bb < a1) {
+      const double x0 = X[(long)a * 2 * cx + bb], x1 = X[(long)a * 2 * cx + cx + bb];
+      v = (o == 0) ? (d00 * x0 + d01 * x1) : (d10 * x0 + d11 * x1);
+    }
+    Y[e] = v;
+  }
+  if (threadIdx.x == 0) {
+    c.yb[k + 1] = a1;
+    if (k == 0) c.yb[0] = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// inner products by left environments (FP64)
+//   plain:    E_{k+1}[p][q] = sum_{a,s,b} X_k[a][s][p] E_k[a][b] X2_k[b][s][q]
+//   with MPO: E_{k+1}[p][b'][q] = sum X_k[a][s'][p] M_k[b][s'][s][b'] E_k[a][b][c] X2_k[c][s][q]
+// E lives in the carry area, F in t1, G in theta.
+// ---------------------------------------------------------------------------
+__global__ void k_dot_init(Batch b, WsLayout wl) {
+  if (blockIdx.x >= b.n) return;
+  if (threadIdx.x == 0) b.c[blockIdx.x].ws[wl.carry] = 1.0;
+}
+
+// F[(a, beta)][(s, q)] = sum_c E[(a, beta)][c] X2_k[c][(s, q)]
+__global__ void __launch_bounds__(256) k_dot_f(Batch b, Geo g, WsLayout wl, int with_mpo) {
+  if (blockIdx.z >= b.n) return;
+  Chain& c = b.c[blockIdx.z];
+  const int k = g.k;
+  const int w = with_mpo ? c.mb[k] : 1;
+  const int M = c.xb[k] * w, K = c.x2b[k], N = 2 * g.cap2;
+  const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
+  if (m0 >= M) return;
+  View A{c.ws + wl.carry, g.cap2, 1};
+  View B{c.x2 + (long)k * slot(g.cap2, 2), 2 * g.cap2, 1};
+  gemm_tile<0>(M, N, 0, K, A, B, c.ws + wl.t1, 2 * g.cap2, 1, 1.0, 0.0, m0, n0);
+}
+
+// G[a][(s', beta')][q] = sum_{beta, s} Mt[(s', beta')][(beta, s)] F[a][(beta, s)][q]
+__global__ void __launch_bounds__(256) k_dot_g(Batch b, Geo g, WsLayout wl) {
+  const int ci = blockIdx.z / g.capx, a = blockIdx.z % g.capx;
+  if (ci >= b.n) return;
+  Chain& c = b.c[ci];
+  const int k = g.k;
+  if (a >= c.xb[k]) return;
+  const int w = c.mb[k], w2 = c.mb[k + 1];
+  const int M = 2 * w2, K = 2 * w, N = g.cap2;
+  const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
+  if (m0 >= M) return;
+  View A{c.ws + wl.mt + (size_t)k * (2 * g.W) * (2 * g.W), 2 * w, 1};
+  View B{c.ws + wl.t1 + (long)a * w * 2 * g.cap2, g.cap2, 1};
+  gemm_tile<0>(M, N, 0, K, A, B, c.ws + wl.theta + (long)a * 2 * w2 * g.cap2, g.cap2, 1, 1.0, 0.0, m0, n0);
+}
+
+// E'[p][(beta', q)] = sum_{(a, s')} X_k[(a, s')][p] G[(a, s')][(beta', q)]
+__global__ void __launch_bounds__(256) k_dot_e(Batch b, Geo g, WsLayout wl, int with_mpo) {
+  if (blockIdx.z >= b.n) return;
+  Chain& c = b.c[blockIdx.z];
+  const int k = g.k;
+  const int w2 = with_mpo ? c.mb[k + 1] : 1;
+  const int M = c.xb[k + 1], K = 2 * c.xb[k], N = w2 * g.cap2;
+  const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
+  if (m0 >= M || n0 >= N) return;
+  View A{c.x + (long)k * slot(g.capx, 2), 1, g.capx};
+  View B{with_mpo ? (c.ws + wl.theta) : (c.ws + wl.t1), (long)N, 1};
+  gemm_tile<0>(M, N, 0, K, A, B, c.ws + wl.carry, N, 1, 1.0, 0.0, m0, n0);
+}
+
+__global__ void k_dot_finish(Batch b, WsLayout wl) {
+  if (blockIdx.x >= b.n) return;
+  if (threadIdx.x == 0) b.c[blockIdx.x].ws[wl.scal + SC_DOT] = b.c[blockIdx.x].ws[wl.carry];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+namespace {
+__global__ void k_ws_init(Batch b, WsLayout wl) {
+  if (blockIdx.x >= b.n) return;
+  if (threadIdx.x < SC_COUNT) b.c[blockIdx.x].ws[wl.scal + threadIdx.x] = 0.0;
+}
+inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+inline WsLayout lay(const Geo& g) { return WsLayout::make(g.L, std::max(std::max(g.capx, g.capy), g.cap2), g.W, g.splits); }
+}  // namespace
+
+WsLayout WsLayout::make(int L, int C, int W, int splits) {
+  WsLayout w;
+  size_t o = 0;
+  const size_t c = (size_t)C, ww = (size_t)(W > 0 ? W : 1);
+  w.carry = o; o += align64(c * ww * c);
+  w.t1 = o;    o += align64(c * ww * 2 * c);
+  w.theta = o; o += align64(c * 2 * ww * c);
+  w.gpart = o; o += align64((size_t)(splits + 1) * 4 * c * c);
+  w.tmpA = o;  o += align64(4 * c * c);
+  w.mt = o;    o += align64((size_t)L * 4 * ww * ww);
+  w.scal = o;  o += 64;
+  w.total = o;
+  w.splits = splits;
+  return w;
+}
+
+namespace qttk {
+
+hipError_t init(int lds_bytes) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_zip_factor, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_rl_svd, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_lr_qr, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  return e;
+}
+
+void ws_init(const Batch& b, const WsLayout& wl, hipStream_t s) {
+  hipLaunchKernelGGL(k_ws_init, dim3(b.n), dim3(64), 0, s, b, wl);
+}
+
+void zip_init(const Batch& b, const WsLayout& wl, hipStream_t s) {
+  hipLaunchKernelGGL(k_zip_init, dim3(b.n), dim3(64), 0, s, b, wl);
+}
+
+void mpo_transpose(const Batch& b, const Geo& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_mpo_transpose, dim3(g.L, b.n), dim3(256), 0, s, b, g, lay(g));
+}
+
+void zip_t1(const Batch& b, const Geo& g, hipStream_t s) {
+  dim3 grid(cdiv(2 * g.capx, TILE), cdiv(g.capy * g.W, TILE), b.n);
+  const WsLayout wl = lay(g);
+  if (g.mode == 0) hipLaunchKernelGGL(k_zip_t1<0>, grid, dim3(256), 0, s, b, g, wl);
+  else if (g.mode == 1) hipLaunchKernelGGL(k_zip_t1<1>, grid, dim3(256), 0, s, b, g, wl);
+  else hipLaunchKernelGGL(k_zip_t1<2>, grid, dim3(256), 0, s, b, g, wl);
+}
+
+void zip_t2(const Batch& b, const Geo& g, hipStream_t s) {
+  dim3 grid(cdiv(g.capx, TILE), cdiv(2 * g.W, TILE), b.n * g.capy);
+  const WsLayout wl = lay(g);
+  if (g.mode == 0) hipLaunchKernelGGL(k_zip_t2<0>, grid, dim3(256), 0, s, b, g, wl);
+  else if (g.mode == 1) hipLaunchKernelGGL(k_zip_t2<1>, grid, dim3(256), 0, s, b, g, wl);
+  else hipLaunchKernelGGL(k_zip_t2<2>, grid, dim3(256), 0, s, b, g, wl);
+}
+
+void zip_gram(const Batch& b, const Geo& g, hipStream_t s) {
+  dim3 grid(cdiv(2 * g.capy, TILE), cdiv(2 * g.capy, TILE), b.n * g.splits);
+  hipLaunchKernelGGL(k_zip_gram, grid, dim3(256), 0, s, b, g, lay(g));
+}
+
+void zip_factor(const Batch& b, const Geo& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_zip_factor, dim3(b.n), dim3(FACT_THREADS), g.lds, s, b, g, lay(g));
+}
+
+void zip_carry(const Batch& b, const Geo& g, hipStream_t s) {
+  dim3 grid(cdiv(g.W * g.capx, TILE), cdiv(g.capy, TILE), b.n);
+  hipLaunchKernelGGL(k_zip_carry, grid, dim3(256), 0, s, b, g, lay(g));
+}
+
+void zip_last(const Batch& b, const Geo& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_zip_last, dim3(b.n), dim3(256), 0, s, b, g, lay(g));
+}
+
+void rl_svd_site(const Batch& b, const Geo& g, int from_tmp, hipStream_t s) {
+  hipLaunchKernelGGL(k_rl_svd, dim3(b.n), dim3(FACT_THREADS), g.lds, s, b, g, lay(g), from_tmp);
+}
+
+void rl_finish(const Batch& b, const Geo& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_tmp_to_slot, dim3(b.n), dim3(256), 0, s, b, g, lay(g), 0);
+}
+
+void lr_qr_site(const Batch& b, const Geo& g, int from_tmp, hipStream_t s) {
+  hipLaunchKernelGGL(k_lr_qr, dim3(b.n), dim3(FACT_THREADS), g.lds, s, b, g, lay(g), from_tmp);
+}
+
+void lr_finish(const Batch& b, const Geo& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_tmp_to_slot, dim3(b.n), dim3(256), 0, s, b, g, lay(g), g.L - 1);
+}
+
+void direct_sum(const Batch& b, const Geo& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_direct_sum, dim3(g.L, b.n), dim3(256), 0, s, b, g);
+}
+
+void copy_mps(const Batch& b, const Geo& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy, dim3(g.L, b.n), dim3(256), 0, s, b, g);
+}
+
+void diag_mpo(const Batch& b, const Geo& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_mpo, dim3(g.L, b.n), dim3(256), 0, s, b, g);
+}
+
+void apply_local(const Batch& b, const Geo& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_apply_local, dim3(g.L, b.n), dim3(256), 0, s, b, g);
+}
+
+void dot_init(const Batch& b, const Geo& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_init, dim3(b.n), dim3(64), 0, s, b, lay(g));
+}
+
+void dot_step(const Batch& b, const Geo& g, int with_mpo, hipStream_t s) {
+  const WsLayout wl = lay(g);
+  const int W = with_mpo ? g.W : 1;
+  hipLaunchKernelGGL(k_dot_f, dim3(cdiv(2 * g.cap2, TILE), cdiv(g.capx * W, TILE), b.n), dim3(256), 0, s, b,
+                     g, wl, with_mpo);
+  if (with_mpo)
+    hipLaunchKernelGGL(k_dot_g, dim3(cdiv(g.cap2, TILE), cdiv(2 * g.W, TILE), b.n * g.capx), dim3(256), 0, s,
+                       b, g, wl);
+  hipLaunchKernelGGL(k_dot_e, dim3(cdiv(W * g.cap2, TILE), cdiv(g.capx, TILE), b.n), dim3(256), 0, s, b, g, wl,
+                     with_mpo);
+}
+
+void dot_finish(const Batch& b, const Geo& g, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_finish, dim3(b.n), dim3(64), 0, s, b, lay(g));
+}
+
+}  // namespace qttk

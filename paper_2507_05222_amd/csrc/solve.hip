@@ -1,0 +1,871 @@
+// Single-site variational (ALS / one-site DMRG) solver of A x = b in TT format
+// (Sec. 2.1.4 of arxiv 2507.05222: the cost C(x) = 1/2 x.Ax - x.b, local
+// stationarity M_eff x_k = b_eff, DMRG-style sweeps; the local products use the
+// "fast matvec" of App. G, i.e. successive contractions with the environment
+// tensors instead of an assembled M_eff).
+//
+// Every contraction is a batched GEMM whose dimensions are products of bond
+// dimensions read on the device (GemmJob with bond expressions), so a sweep is
+// enqueued without host synchronisation; the host reads the FP64 residual once
+// per sweep to decide whether to continue.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/qtt.h"
+#include "device_common.h"
+
+namespace {
+
+constexpr int GB = 4;   // chains per solver launch
+
+// value = mul * p1[i1] * p2[i2] + add   (a null pointer counts as 1)
+struct IE {
+  const int* p1; const int* p2; int i1, i2, mul, add;
+};
+__device__ __forceinline__ int ev(const IE& e) {
+  int v = e.mul;
+  if (e.p1) v *= e.p1[e.i1];
+  if (e.p2) v *= e.p2[e.i2];
+  return v + e.add;
+}
+inline IE C_(int v) { return IE{nullptr, nullptr, 0, 0, 0, v}; }
+inline IE B1(const int* p, int i, int mul = 1, int add = 0) { return IE{p, nullptr, i, 0, mul, add}; }
+inline IE B2(const int* p, int i, const int* q, int j, int mul = 1) { return IE{p, q, i, j, mul, 0}; }
+
+struct GemmJob {
+  const double* A; IE ars, acs;
+  const double* B; IE brs, bcs;
+  double* C; IE crs, ccs;
+  IE M, N, K;
+  IE nb, sa, sb, sc;        // batch count and batch strides
+  const double* skip;       // if non-null and *skip != 0, the job is skipped
+};
+struct GemmBatch {
+  int n, maxb;
+  GemmJob j[GB];
+};
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_gemm_jobs(GemmBatch gb) {
+  const int ci = blockIdx.z / gb.maxb, bi = blockIdx.z % gb.maxb;
+  if (ci >= gb.n) return;
+  const GemmJob& j = gb.j[ci];
+  if (j.skip && *j.skip != 0.0) return;
+  if (bi >= ev(j.nb)) return;
+  const int M = ev(j.M), N = ev(j.N), K = ev(j.K);
+  const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
+  if (m0 >= M || n0 >= N) return;
+  View A{j.A + (long)bi * ev(j.sa), ev(j.ars), ev(j.acs)};
+  View B{j.B + (long)bi * ev(j.sb), ev(j.brs), ev(j.bcs)};
+  gemm_tile<MODE>(M, N, 0, K, A, B, j.C + (long)bi * ev(j.sc), ev(j.crs), ev(j.ccs), 1.0, 0.0, m0, n0);
+}
+
+inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+void run_jobs(const GemmBatch& gb, int maxM, int maxN, int mode, hipStream_t s) {
+  dim3 grid(cdiv(maxN, TILE), cdiv(maxM, TILE), gb.n * gb.maxb);
+  if (mode == 0) hipLaunchKernelGGL(k_gemm_jobs<0>, grid, dim3(256), 0, s, gb);
+  else if (mode == 1) hipLaunchKernelGGL(k_gemm_jobs<1>, grid, dim3(256), 0, s, gb);
+  else hipLaunchKernelGGL(k_gemm_jobs<2>, grid, dim3(256), 0, s, gb);
+}
+
+// ---------------------------------------------------------------------------
+// per-chain data of the solver
+// ---------------------------------------------------------------------------
+struct SChain {
+  const double* A; const int* ab;   // MPO (wcap) and its device bonds
+  const double* b; const int* bb;   // right-hand side (cap cb)
+  double* x; int* xb;               // bra: unknown / fitted train (cap cx), updated in place
+  const double* kx; const int* kxb; // ket: the train the environments contract with (cap ck)
+  double* ws;                       // solver workspace
+  int* iws;                         // integer workspace (A^T A bonds)
+};
+struct SBatch {
+  int n;
+  SChain c[GB];
+};
+struct SGeo {
+  int L, k, cx, cb, wcap, W;
+  int ck;           // slot capacity of the ket train
+  double ltol;      // local CG relative tolerance
+  int maxit;        // CG iterations per local problem
+  int lds;          // dynamic LDS budget (bytes) of the gauge-move kernels
+};
+
+// workspace layout (doubles)
+struct SLay {
+  size_t LA, RA, Lb, Rb, F1, F2, F3, Mt, Mt2, beff, r, p, Ap, dinv, sc, A2, tmpA, gp, total;
+  size_t env, envb;
+  static SLay make(int L, int cx, int ck, int cb, int W) {
+    SLay l;
+    size_t o = 0;
+    auto al = [](size_t v) { return (v + 63) & ~size_t(63); };
+    l.env = (size_t)cx * W * ck;
+    l.envb = (size_t)cx * cb;
+    const size_t C = std::max(std::max(cx, ck), cb);
+    l.LA = o; o += al((L + 1) * l.env);
+    l.RA = o; o += al((L + 1) * l.env);
+    l.Lb = o; o += al((L + 1) * l.envb);
+    l.Rb = o; o += al((L + 1) * l.envb);
+    l.F1 = o; o += al(C * W * 2 * C);
+    l.F2 = o; o += al(C * 2 * W * C);   // also holds M_k T[a] of the last projection
+    l.F3 = o; o += al(2 * C * C);
+    l.Mt = o; o += al((size_t)L * 4 * W * W);
+    l.Mt2 = o; o += al((size_t)L * 4 * W * W);
+    l.beff = o; o += al(2 * (size_t)cx * cx);
+    l.r = o; o += al(2 * (size_t)cx * cx);
+    l.p = o; o += al(2 * (size_t)cx * cx);
+    l.Ap = o; o += al(2 * (size_t)cx * cx);
+    l.dinv = o; o += al(2 * (size_t)cx * cx);
+    l.sc = o; o += 64;
+    l.A2 = o; o += al((size_t)L * (size_t)W * W * 4 * W * W);
+    l.tmpA = o; o += al(4 * (size_t)cx * cx);
+    l.gp = o; o += al(4 * 4 * (size_t)cx * cx);
+    l.total = o;
+    return l;
+  }
+};
+// scalar slots
+enum { S_RZ = 0, S_DONE, S_ITER, S_BN2, S_RN2, S_ITERS_TOTAL, S_COUNT };
+
+__device__ __forceinline__ size_t sl2(int cap) { return (size_t)cap * 2 * cap; }
+
+// MPO transposes of site k: Mt[(s' w2 + b')][(b 2 + s)] = A[b][s'][s][b'];
+// Mt2[(b 2 + s)][(s' w2 + b')] = A[b][s'][s][b'].
+__global__ void k_transposes(SBatch sb, SGeo g, SLay l) {
+  const int k = blockIdx.x;
+  if (blockIdx.y >= sb.n) return;
+  const SChain& c = sb.c[blockIdx.y];
+  const int w = c.ab[k], w2 = c.ab[k + 1];
+  const double* Ak = c.A + (long)k * g.wcap * 4 * g.wcap;
+  double* T = c.ws + l.Mt + (size_t)k * 4 * g.W * g.W;
+  double* T2 = c.ws + l.Mt2 + (size_t)k * 4 * g.W * g.W;
+  for (int e = threadIdx.x; e < 4 * w * w2; e += blockDim.x) {
+    const int i = e / (2 * w), kk = e % (2 * w);
+    const int sp = i / w2, bp = i % w2, b = kk / 2, s = kk % 2;
+    const double v = Ak[(long)b * 4 * g.wcap + sp * 2 * g.wcap + s * g.wcap + bp];
+    T[e] = v;
+    T2[(size_t)kk * (2 * w2) + i] = v;
+  }
+}
+
+// A^T A as an MPO (bond w^2): C[(b1 w + b2)][o][i][(c1 w' + c2)] = sum_m A[b1][m][o][c1] A[b2][m][i][c2]
+__global__ void k_mpo_ata(SBatch sb, SGeo g, SLay l) {
+  const int k = blockIdx.x;
+  if (blockIdx.y >= sb.n) return;
+  const SChain& c = sb.c[blockIdx.y];
+  const int w = c.ab[k], w2 = c.ab[k + 1], wc = g.wcap, W2 = g.W * g.W;
+  const double* Ak = c.A + (long)k * wc * 4 * wc;
+  double* Ck = c.ws + l.A2 + (size_t)k * W2 * 4 * W2;
+  for (int e = threadIdx.x; e < W2 * 4 * W2; e += blockDim.x) {
+    const int bb = e / (4 * W2), oi = (e / W2) % 4, cc = e % W2;
+    const int b1 = bb / g.W, b2 = bb % g.W, c1 = cc / g.W, c2 = cc % g.W, o = oi / 2, i = oi % 2;
+    double v = 0.0;
+    if (b1 < w && b2 < w && c1 < w2 && c2 < w2) {
+      for (int m = 0; m < 2; ++m)
+        v += Ak[(long)b1 * 4 * wc + m * 2 * wc + o * wc + c1] * Ak[(long)b2 * 4 * wc + m * 2 * wc + i * wc + c2];
+    }
+    // compact bond index b1*w + b2 (actual bonds) inside the wc^2 slot
+    const int bc = (b1 < w && b2 < w) ? b1 * w + b2 : -1;
+    const int ccc = (c1 < w2 && c2 < w2) ? c1 * w2 + c2 : -1;
+    if (bc >= 0 && ccc >= 0) Ck[(size_t)bc * 4 * W2 + oi * W2 + ccc] = v;
+  }
+  if (threadIdx.x == 0) {
+    c.iws[k + 1] = w2 * w2;
+    if (k == 0) c.iws[0] = 1;
+  }
+}
+
+// environment initialisation: LA_0 = RA_L = Lb_0 = Rb_L = [1]; counters zero
+__global__ void k_env_init(SBatch sb, SGeo g, SLay l) {
+  if (blockIdx.x >= sb.n) return;
+  const SChain& c = sb.c[blockIdx.x];
+  if (threadIdx.x == 0) {
+    c.ws[l.LA] = 1.0;
+    c.ws[l.RA + (size_t)g.L * l.env] = 1.0;
+    c.ws[l.Lb] = 1.0;
+    c.ws[l.Rb + (size_t)g.L * l.envb] = 1.0;
+  }
+  if (threadIdx.x < S_COUNT) c.ws[l.sc + threadIdx.x] = 0.0;
+}
+
+// Jacobi preconditioner of the local system: 1 / diag(M_eff)
+__global__ void k_precond(SBatch sb, SGeo g, SLay l) {
+  if (blockIdx.y >= sb.n) return;
+  const SChain& c = sb.c[blockIdx.y];
+  const int k = g.k, cx = g.cx;
+  const int nl = c.xb[k], nr = c.xb[k + 1], w = c.ab[k], w2 = c.ab[k + 1];
+  const double* LA = c.ws + l.LA + (size_t)k * l.env;
+  const double* RA = c.ws + l.RA + (size_t)(k + 1) * l.env;
+  const double* Ak = c.A + (long)k * g.wcap * 4 * g.wcap;
+  double* dinv = c.ws + l.dinv;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 2 * cx * cx; e += gridDim.x * blockDim.x) {
+    const int a = e / (2 * cx), s = (e / cx) % 2, cc = e % cx;
+    double v = 0.0;
+    if (a < nl && cc < nr) {
+      for (int b = 0; b < w; ++b) {
+        const double la = LA[((size_t)a * w + b) * cx + a];
+        if (la == 0.0) continue;
+        for (int b2 = 0; b2 < w2; ++b2)
+          v += la * Ak[(long)b * 4 * g.wcap + s * 2 * g.wcap + s * g.wcap + b2] * RA[((size_t)cc * w2 + b2) * cx + cc];
+      }
+    }
+    dinv[e] = v > 0.0 ? 1.0 / v : 1.0;
+  }
+}
+
+// Local CG (one workgroup per chain): vectors in [a][s][c] layout with row
+// stride cx; the unknown is core k of x itself.
+__device__ double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < nw; ++i) t += red[i];
+  return t;
+}
+
+__global__ void __launch_bounds__(1024) k_cg_init(SBatch sb, SGeo g, SLay l) {
+  __shared__ double red[16];
+  if (blockIdx.x >= sb.n) return;
+  const SChain& c = sb.c[blockIdx.x];
+  const int k = g.k, cx = g.cx;
+  const int nl = c.xb[k], nr = c.xb[k + 1];
+  double* sc = c.ws + l.sc;
+  const double* beff = c.ws + l.beff;
+  const double* Ax = c.ws + l.Ap;
+  double* r = c.ws + l.r;
+  double* p = c.ws + l.p;
+  const double* dinv = c.ws + l.dinv;
+  double rz = 0, bn = 0, rn = 0;
+  for (int e = threadIdx.x; e < 2 * cx * cx; e += blockDim.x) {
+    const int a = e / (2 * cx), cc = e % cx;
+    double rv = 0, pv = 0;
+    if (a < nl && cc < nr) {
+      rv = beff[e] - Ax[e];
+      pv = dinv[e] * rv;
+      rz += rv * pv; bn += beff[e] * beff[e]; rn += rv * rv;
+    }
+    r[e] = rv; p[e] = pv;
+  }
+  rz = block_sum(rz, red);
+  bn = block_sum(bn, red);
+  rn = block_sum(rn, red);
+  if (threadIdx.x == 0) {
+    sc[S_RZ] = rz; sc[S_BN2] = bn; sc[S_RN2] = rn; sc[S_ITER] = 0;
+    sc[S_DONE] = (bn == 0.0 || rn <= g.ltol * g.ltol * bn || g.maxit <= 0) ? 1.0 : 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_cg_step(SBatch sb, SGeo g, SLay l) {
+  __shared__ double red[16];
+  if (blockIdx.x >= sb.n) return;
+  const SChain& c = sb.c[blockIdx.x];
+  double* sc = c.ws + l.sc;
+  if (sc[S_DONE] != 0.0) return;
+  const int k = g.k, cx = g.cx;
+  const int nl = c.xb[k], nr = c.xb[k + 1];
+  double* x = c.x + (long)k * sl2(cx);
+  double* r = c.ws + l.r;
+  double* p = c.ws + l.p;
+  const double* Ap = c.ws + l.Ap;
+  const double* dinv = c.ws + l.dinv;
+  double pAp = 0;
+  for (int e = threadIdx.x; e < 2 * cx * cx; e += blockDim.x) pAp += p[e] * Ap[e];
+  pAp = block_sum(pAp, red);
+  const double rz = sc[S_RZ];
+  const double alpha = pAp > 0.0 ? rz / pAp : 0.0;
+  double rn = 0, rz2 = 0;
+  for (int e = threadIdx.x; e < 2 * cx * cx; e += blockDim.x) {
+    const int a = e / (2 * cx), cc = e % cx;
+    if (a < nl && cc < nr) {
+      x[e] += alpha * p[e];
+      const double rv = r[e] - alpha * Ap[e];
+      r[e] = rv;
+      rn += rv * rv;
+      rz2 += rv * dinv[e] * rv;
+    }
+  }
+  rn = block_sum(rn, red);
+  rz2 = block_sum(rz2, red);
+  const double it = sc[S_ITER] + 1.0;
+  const bool done = !(pAp > 0.0) || rn <= g.ltol * g.ltol * sc[S_BN2] || it >= g.maxit;
+  if (!done) {
+    const double beta = rz > 0.0 ? rz2 / rz : 0.0;
+    for (int e = threadIdx.x; e < 2 * cx * cx; e += blockDim.x) p[e] = dinv[e] * r[e] + beta * p[e];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    sc[S_RZ] = rz2; sc[S_RN2] = rn; sc[S_ITER] = it;
+    sc[S_ITERS_TOTAL] += 1.0;
+    sc[S_DONE] = done ? 1.0 : 0.0;
+  }
+}
+
+// Right-to-left gauge move at site k by Householder LQ (bond kept):
+// Y_k (b_k x 2 b_{k+1}): Y_k^T = Q R  ->  core k <- Q^T, tmp <- Y_{k-1} R^T.
+__global__ void __launch_bounds__(1024) k_rl_qr(SBatch sb, SGeo g, SLay l) {
+  extern __shared__ double smem[];
+  __shared__ double rdiag[512], tau[512];
+  if (blockIdx.x >= sb.n) return;
+  const SChain& c = sb.c[blockIdx.x];
+  const int k = g.k, cap = g.cx;
+  const int nb = c.xb[k], mb = c.xb[k + 1];
+  const int m = 2 * mb, n = nb, r = m < n ? m : n;
+  const size_t need = ((size_t)m * n + (size_t)m * r) * sizeof(double);
+  // The budget passed in smem size is checked by the host; fall back to global scratch otherwise.
+  double* X = (need <= (size_t)g.lds) ? smem : (c.ws + l.gp);
+  double* Q = X + (size_t)m * n;
+  double* Yk = c.x + (long)k * sl2(cap);
+  for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
+    const int a = e / m, rho = e % m, s = rho / mb, bb = rho % mb;
+    X[e] = Yk[(long)a * 2 * cap + s * cap + bb];
+  }
+  __syncthreads();
+  householder(X, m, n, rdiag, tau);
+  householder_q(X, m, n, tau, Q);
+  const int S = cap * 2 * cap;
+  for (int e = threadIdx.x; e < S; e += blockDim.x) {
+    const int j = e / (2 * cap), s = (e / cap) % 2, bb = e % cap;
+    Yk[e] = (j < r && bb < mb) ? Q[(long)j * m + s * mb + bb] : 0.0;
+  }
+  // Y_{k-1} <- Y_{k-1} R^T  (R: r x n upper trapezoidal; R^T: n x r)
+  const int np = c.xb[k - 1];
+  double* Yp = c.x + (long)(k - 1) * sl2(cap);
+  double* T = c.ws + l.tmpA;
+  __syncthreads();
+  for (int e = threadIdx.x; e < S; e += blockDim.x) {
+    const int a0 = e / (2 * cap), s = (e / cap) % 2, j = e % cap;
+    double v = 0.0;
+    if (a0 < np && j < r) {
+      const double* yrow = Yp + (long)a0 * 2 * cap + s * cap;
+      // (Y R^T)[., j] = sum_t Y[., t] R[j][t], R[j][j] = rdiag, R[j][t>j] = X[t][j]
+      v = yrow[j] * rdiag[j];
+      for (int t = j + 1; t < n; ++t) v += yrow[t] * X[(long)t * m + j];
+    }
+    T[e] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < S; e += blockDim.x) Yp[e] = T[e];
+  if (threadIdx.x == 0) c.xb[k] = r;
+}
+
+// Left-to-right gauge move at site k by Householder QR (bond kept):
+// core k (2 b_k x b_{k+1}) = Q R -> core k <- Q, core k+1 <- R core k+1.
+__global__ void __launch_bounds__(1024) k_lr_qr_keep(SBatch sb, SGeo g, SLay l) {
+  extern __shared__ double smem[];
+  __shared__ double rdiag[512], tau[512];
+  if (blockIdx.x >= sb.n) return;
+  const SChain& c = sb.c[blockIdx.x];
+  const int k = g.k, cap = g.cx;
+  const int m = 2 * c.xb[k], n = c.xb[k + 1];
+  const int r = m < n ? m : n;
+  const size_t need = ((size_t)m * n + (size_t)m * r) * sizeof(double);
+  double* X = (need <= (size_t)g.lds) ? smem : (c.ws + l.gp);
+  double* Q = X + (size_t)m * n;
+  double* Yk = c.x + (long)k * sl2(cap);
+  for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
+    const int j = e / m, i = e % m;
+    X[e] = Yk[(long)i * cap + j];
+  }
+  __syncthreads();
+  householder(X, m, n, rdiag, tau);
+  householder_q(X, m, n, tau, Q);
+  const int S = cap * 2 * cap;
+  for (int e = threadIdx.x; e < S; e += blockDim.x) {
+    const int i = e / cap, j = e % cap;
+    Yk[e] = (i < m && j < r) ? Q[(long)j * m + i] : 0.0;
+  }
+  const int n2 = c.xb[k + 2];
+  double* Yn = c.x + (long)(k + 1) * sl2(cap);
+  double* T = c.ws + l.tmpA;
+  __syncthreads();
+  for (int e = threadIdx.x; e < S; e += blockDim.x) {
+    const int j = e / (2 * cap), s = (e / cap) % 2, bb = e % cap;
+    double v = 0.0;
+    if (j < r && bb < n2) {
+      v = rdiag[j] * Yn[(long)j * 2 * cap + s * cap + bb];
+      for (int t = j + 1; t < n; ++t) v += X[(long)t * m + j] * Yn[(long)t * 2 * cap + s * cap + bb];
+    }
+    T[e] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < S; e += blockDim.x) Yn[e] = T[e];
+  if (threadIdx.x == 0) c.xb[k + 1] = r;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct Solver {
+  SBatch sb;
+  SGeo g;
+  SLay l;
+  int mode;
+  hipStream_t s;
+  int lds;
+
+  GemmBatch batch(int maxb) const {
+    GemmBatch gb;
+    std::memset(&gb, 0, sizeof(gb));
+    gb.n = sb.n;
+    gb.maxb = maxb;
+    return gb;
+  }
+  static void one(GemmJob& j) {
+    j.nb = C_(1); j.sa = C_(0); j.sb = C_(0); j.sc = C_(0); j.skip = nullptr;
+  }
+
+  // LA_{k+1} from LA_k (contraction of site k): LA[(a, b)][a'] with bra index a
+  // (cap cx) and ket index a' (cap ck). Steps 1-2 are shared with the projection.
+  void la_steps12(int k, int mmode) {
+    const int ck = g.ck, W = g.W;
+    GemmBatch g1 = batch(1), g2 = batch(g.cx);
+    for (int i = 0; i < sb.n; ++i) {
+      const SChain& c = sb.c[i];
+      const double* LAk = c.ws + l.LA + (size_t)k * l.env;
+      const double* Kk = c.kx + (size_t)k * ck * 2 * ck;
+      GemmJob& a = g1.j[i]; one(a);    // F[(a,b)][(s,c')] = LA[(a,b)][a'] K[a'][(s,c')]
+      a.A = LAk; a.ars = C_(ck); a.acs = C_(1);
+      a.B = Kk; a.brs = C_(2 * ck); a.bcs = C_(1);
+      a.C = c.ws + l.F1; a.crs = C_(2 * ck); a.ccs = C_(1);
+      a.M = B2(c.xb, k, c.ab, k); a.N = C_(2 * ck); a.K = B1(c.kxb, k);
+      GemmJob& b = g2.j[i]; one(b);    // G[a][(s',b')][c'] = Mt[(s',b')][(b,s)] F[a][(b,s)][c']
+      b.A = c.ws + l.Mt + (size_t)k * 4 * W * W; b.ars = B1(c.ab, k, 2); b.acs = C_(1);
+      b.B = c.ws + l.F1; b.brs = C_(ck); b.bcs = C_(1);
+      b.C = c.ws + l.F2; b.crs = C_(ck); b.ccs = C_(1);
+      b.M = B1(c.ab, k + 1, 2); b.N = C_(ck); b.K = B1(c.ab, k, 2);
+      b.nb = B1(c.xb, k); b.sb = B1(c.ab, k, 2 * ck); b.sc = B1(c.ab, k + 1, 2 * ck);
+    }
+    run_jobs(g1, g.cx * W, 2 * ck, mmode, s);
+    run_jobs(g2, 2 * W, ck, mmode, s);
+  }
+  // LA_{k+1}[p][(b', q)] = sum_{(a, s')} X_k[(a, s')][p] G[(a, s')][(b', q)]
+  void la_step3(int k, int mmode) {
+    const int cx = g.cx, ck = g.ck, W = g.W;
+    GemmBatch g3 = batch(1);
+    for (int i = 0; i < sb.n; ++i) {
+      const SChain& c = sb.c[i];
+      GemmJob& d = g3.j[i]; one(d);
+      d.A = c.x + (size_t)k * cx * 2 * cx; d.ars = C_(1); d.acs = C_(cx);
+      d.B = c.ws + l.F2; d.brs = B1(c.ab, k + 1, ck); d.bcs = C_(1);
+      d.C = c.ws + l.LA + (size_t)(k + 1) * l.env; d.crs = B1(c.ab, k + 1, ck); d.ccs = C_(1);
+      d.M = B1(c.xb, k + 1); d.N = B1(c.ab, k + 1, ck); d.K = B1(c.xb, k, 2);
+    }
+    run_jobs(g3, cx, W * ck, mmode, s);
+  }
+  void la_update(int k, int mmode = 0) {
+    la_steps12(k, mmode);
+    la_step3(k, mmode);
+  }
+
+  // RA_k from RA_{k+1}: RA[(c, b)][c'] with bra index c (cap cx), ket index c' (cap ck)
+  void ra_update(int k, int mmode = 0) {
+    const int cx = g.cx, ck = g.ck, W = g.W;
+    GemmBatch g1 = batch(1), g2 = batch(cx), g3 = batch(1);
+    for (int i = 0; i < sb.n; ++i) {
+      const SChain& c = sb.c[i];
+      const double* RAn = c.ws + l.RA + (size_t)(k + 1) * l.env;
+      double* RAk = c.ws + l.RA + (size_t)k * l.env;
+      const double* Xk = c.x + (size_t)k * cx * 2 * cx;
+      const double* Kk = c.kx + (size_t)k * ck * 2 * ck;
+      GemmJob& a = g1.j[i]; one(a);    // F[(c,s')][(b',d')] = X[(c,s')][d] RA[d][(b',d')]
+      a.A = Xk; a.ars = C_(cx); a.acs = C_(1);
+      a.B = RAn; a.brs = B1(c.ab, k + 1, ck); a.bcs = C_(1);
+      a.C = c.ws + l.F1; a.crs = B1(c.ab, k + 1, ck); a.ccs = C_(1);
+      a.M = B1(c.xb, k, 2); a.N = B1(c.ab, k + 1, ck); a.K = B1(c.xb, k + 1);
+      GemmJob& b = g2.j[i]; one(b);    // G[c][(b,s)][d'] = Mt2[(b,s)][(s',b')] F[c][(s',b')][d']
+      b.A = c.ws + l.Mt2 + (size_t)k * 4 * W * W; b.ars = B1(c.ab, k + 1, 2); b.acs = C_(1);
+      b.B = c.ws + l.F1; b.brs = C_(ck); b.bcs = C_(1);
+      b.C = c.ws + l.F2; b.crs = C_(ck); b.ccs = C_(1);
+      b.M = B1(c.ab, k, 2); b.N = C_(ck); b.K = B1(c.ab, k + 1, 2);
+      b.nb = B1(c.xb, k); b.sb = B1(c.ab, k + 1, 2 * ck); b.sc = B1(c.ab, k, 2 * ck);
+      GemmJob& d = g3.j[i]; one(d);    // RA_k[(c,b)][c'] = G[(c,b)][(s,d')] K[c'][(s,d')]
+      d.A = c.ws + l.F2; d.ars = C_(2 * ck); d.acs = C_(1);
+      d.B = Kk; d.brs = C_(1); d.bcs = C_(2 * ck);
+      d.C = RAk; d.crs = C_(ck); d.ccs = C_(1);
+      d.M = B2(c.xb, k, c.ab, k); d.N = B1(c.kxb, k); d.K = C_(2 * ck);
+    }
+    run_jobs(g1, 2 * cx, W * ck, mmode, s);
+    run_jobs(g2, 2 * W, ck, mmode, s);
+    run_jobs(g3, cx * W, ck, mmode, s);
+  }
+
+  // Variational projection of M x onto the frame of the bra at site k:
+  // X_k <- LA_k M_k K_k RA_{k+1} (leaves G = M_k T[a] in F2 for la_step3).
+  void project(int k, int mmode) {
+    const int cx = g.cx, ck = g.ck, W = g.W;
+    la_steps12(k, mmode);
+    GemmBatch g3 = batch(1);
+    for (int i = 0; i < sb.n; ++i) {
+      const SChain& c = sb.c[i];
+      GemmJob& d = g3.j[i]; one(d);    // X[(a,s')][c] = G[(a,s')][(b',c')] RA[c][(b',c')]
+      d.A = c.ws + l.F2; d.ars = B1(c.ab, k + 1, ck); d.acs = C_(1);
+      d.B = c.ws + l.RA + (size_t)(k + 1) * l.env; d.brs = C_(1); d.bcs = B1(c.ab, k + 1, ck);
+      d.C = c.x + (size_t)k * cx * 2 * cx; d.crs = C_(cx); d.ccs = C_(1);
+      d.M = B1(c.xb, k, 2); d.N = B1(c.xb, k + 1); d.K = B1(c.ab, k + 1, ck);
+    }
+    run_jobs(g3, 2 * cx, cx, mmode, s);
+  }
+
+  void lb_update(int k) {
+    const int cx = g.cx, cb = g.cb;
+    GemmBatch g1 = batch(1), g2 = batch(1);
+    for (int i = 0; i < sb.n; ++i) {
+      const SChain& c = sb.c[i];
+      const double* Xk = c.x + (size_t)k * cx * 2 * cx;
+      const double* Bk = c.b + (size_t)k * cb * 2 * cb;
+      GemmJob& a = g1.j[i]; one(a);    // F[a][(s,g)] = Lb[a][al] B[al][(s,g)]
+      a.A = c.ws + l.Lb + (size_t)k * l.envb; a.ars = C_(cb); a.acs = C_(1);
+      a.B = Bk; a.brs = C_(2 * cb); a.bcs = C_(1);
+      a.C = c.ws + l.F3; a.crs = C_(2 * cb); a.ccs = C_(1);
+      a.M = B1(c.xb, k); a.N = C_(2 * cb); a.K = B1(c.bb, k);
+      GemmJob& b = g2.j[i]; one(b);    // Lb'[p][g] = X[(a,s)][p] F[(a,s)][g]
+      b.A = Xk; b.ars = C_(1); b.acs = C_(cx);
+      b.B = c.ws + l.F3; b.brs = C_(cb); b.bcs = C_(1);
+      b.C = c.ws + l.Lb + (size_t)(k + 1) * l.envb; b.crs = C_(cb); b.ccs = C_(1);
+      b.M = B1(c.xb, k + 1); b.N = B1(c.bb, k + 1); b.K = B1(c.xb, k, 2);
+    }
+    run_jobs(g1, cx, 2 * cb, 0, s);
+    run_jobs(g2, cx, cb, 0, s);
+  }
+
+  void rb_update(int k) {
+    const int cx = g.cx, cb = g.cb;
+    GemmBatch g1 = batch(1), g2 = batch(1);
+    for (int i = 0; i < sb.n; ++i) {
+      const SChain& c = sb.c[i];
+      const double* Xk = c.x + (size_t)k * cx * 2 * cx;
+      const double* Bk = c.b + (size_t)k * cb * 2 * cb;
+      GemmJob& a = g1.j[i]; one(a);    // F[(al,s)][d] = B[(al,s)][g] Rb[d][g]
+      a.A = Bk; a.ars = C_(cb); a.acs = C_(1);
+      a.B = c.ws + l.Rb + (size_t)(k + 1) * l.envb; a.brs = C_(1); a.bcs = C_(cb);
+      a.C = c.ws + l.F3; a.crs = C_(cx); a.ccs = C_(1);
+      a.M = B1(c.bb, k, 2); a.N = B1(c.xb, k + 1); a.K = B1(c.bb, k + 1);
+      GemmJob& b = g2.j[i]; one(b);    // Rb[c][al] = X[c][(s,d)] F[(al,s)][d]
+      b.A = Xk; b.ars = C_(2 * cx); b.acs = C_(1);
+      b.B = c.ws + l.F3; b.brs = C_(1); b.bcs = C_(2 * cx);
+      b.C = c.ws + l.Rb + (size_t)k * l.envb; b.crs = C_(cb); b.ccs = C_(1);
+      b.M = B1(c.xb, k); b.N = B1(c.bb, k); b.K = C_(2 * cx);
+    }
+    run_jobs(g1, 2 * cb, cx, 0, s);
+    run_jobs(g2, cx, cb, 0, s);
+  }
+
+  void beff(int k) {
+    const int cx = g.cx, cb = g.cb;
+    GemmBatch g1 = batch(1), g2 = batch(1);
+    for (int i = 0; i < sb.n; ++i) {
+      const SChain& c = sb.c[i];
+      const double* Bk = c.b + (size_t)k * cb * 2 * cb;
+      GemmJob& a = g1.j[i]; one(a);
+      a.A = c.ws + l.Lb + (size_t)k * l.envb; a.ars = C_(cb); a.acs = C_(1);
+      a.B = Bk; a.brs = C_(2 * cb); a.bcs = C_(1);
+      a.C = c.ws + l.F3; a.crs = C_(2 * cb); a.ccs = C_(1);
+      a.M = B1(c.xb, k); a.N = C_(2 * cb); a.K = B1(c.bb, k);
+      GemmJob& b = g2.j[i]; one(b);    // beff[(a,s)][c] = F[(a,s)][g] Rb[c][g]
+      b.A = c.ws + l.F3; b.ars = C_(cb); b.acs = C_(1);
+      b.B = c.ws + l.Rb + (size_t)(k + 1) * l.envb; b.brs = C_(1); b.bcs = C_(cb);
+      b.C = c.ws + l.beff; b.crs = C_(cx); b.ccs = C_(1);
+      b.M = B1(c.xb, k, 2); b.N = B1(c.xb, k + 1); b.K = B1(c.bb, k + 1);
+    }
+    run_jobs(g1, cx, 2 * cb, 0, s);
+    run_jobs(g2, 2 * cx, cx, 0, s);
+  }
+
+  // out = M_eff v at site k (v, out: [a][s][c], row stride cx)
+  void matvec(int k, bool v_is_x, int mmode) {
+    const int cx = g.cx, W = g.W;
+    GemmBatch g1 = batch(1), g2 = batch(cx), g3 = batch(1);
+    for (int i = 0; i < sb.n; ++i) {
+      const SChain& c = sb.c[i];
+      const double* v = v_is_x ? (c.x + (size_t)k * cx * 2 * cx) : (c.ws + l.p);
+      const double* skip = v_is_x ? nullptr : (c.ws + l.sc + S_DONE);
+      GemmJob& a = g1.j[i]; one(a);    // T[(a,b)][(s,c')] = LA[(a,b)][a'] v[a'][(s,c')]
+      a.A = c.ws + l.LA + (size_t)k * l.env; a.ars = C_(cx); a.acs = C_(1);
+      a.B = v; a.brs = C_(2 * cx); a.bcs = C_(1);
+      a.C = c.ws + l.F1; a.crs = C_(2 * cx); a.ccs = C_(1);
+      a.M = B2(c.xb, k, c.ab, k); a.N = C_(2 * cx); a.K = B1(c.xb, k);
+      a.skip = skip;
+      GemmJob& b = g2.j[i]; one(b);    // U[a][(s',b')][c'] = Mt[(s',b')][(b,s)] T[a][(b,s)][c']
+      b.A = c.ws + l.Mt + (size_t)k * 4 * W * W; b.ars = B1(c.ab, k, 2); b.acs = C_(1);
+      b.B = c.ws + l.F1; b.brs = C_(cx); b.bcs = C_(1);
+      b.C = c.ws + l.F2; b.crs = C_(cx); b.ccs = C_(1);
+      b.M = B1(c.ab, k + 1, 2); b.N = C_(cx); b.K = B1(c.ab, k, 2);
+      b.nb = B1(c.xb, k); b.sb = B1(c.ab, k, 2 * cx); b.sc = B1(c.ab, k + 1, 2 * cx);
+      b.skip = skip;
+      GemmJob& d = g3.j[i]; one(d);    // out[(a,s')][c] = U[(a,s')][(b',c')] RA[c][(b',c')]
+      d.A = c.ws + l.F2; d.ars = B1(c.ab, k + 1, cx); d.acs = C_(1);
+      d.B = c.ws + l.RA + (size_t)(k + 1) * l.env; d.brs = C_(1); d.bcs = B1(c.ab, k + 1, cx);
+      d.C = c.ws + l.Ap; d.crs = C_(cx); d.ccs = C_(1);
+      d.M = B1(c.xb, k, 2); d.N = B1(c.xb, k + 1); d.K = B1(c.ab, k + 1, cx);
+      d.skip = skip;
+    }
+    run_jobs(g1, cx * W, 2 * cx, mmode, s);
+    run_jobs(g2, 2 * W, cx, mmode, s);
+    run_jobs(g3, 2 * cx, cx, mmode, s);
+  }
+
+  // Local CG at site k. Iterations are enqueued in chunks of growing length; after
+  // each chunk the host reads the per-chain convergence flags (one small copy) and
+  // stops enqueuing once every chain has converged. Kernels of converged chains
+  // exit at once, so the chunking changes the launch count, not the arithmetic.
+  double* flags = nullptr;   // host pinned, GB entries
+  void local_solve(int k, int mmode) {
+    SGeo gg = g;
+    gg.k = k;
+    beff(k);
+    hipLaunchKernelGGL(k_precond, dim3(8, sb.n), dim3(256), 0, s, sb, gg, l);
+    matvec(k, true, mmode);
+    hipLaunchKernelGGL(k_cg_init, dim3(sb.n), dim3(1024), 0, s, sb, gg, l);
+    int it = 0, chunk = 4;
+    while (it < g.maxit) {
+      const int m = std::min(chunk, g.maxit - it);
+      for (int j = 0; j < m; ++j) {
+        matvec(k, false, mmode);
+        hipLaunchKernelGGL(k_cg_step, dim3(sb.n), dim3(1024), 0, s, sb, gg, l);
+      }
+      it += m;
+      chunk = std::min(2 * chunk, 64);
+      if (it >= g.maxit || !flags) break;
+      for (int i = 0; i < sb.n; ++i)
+        (void)hipMemcpyAsync(flags + i, sb.c[i].ws + l.sc + S_DONE, sizeof(double), hipMemcpyDeviceToHost, s);
+      (void)hipStreamSynchronize(s);
+      bool all = true;
+      for (int i = 0; i < sb.n; ++i) all = all && flags[i] != 0.0;
+      if (all) break;
+    }
+  }
+
+  void lr_move(int k) {
+    SGeo gg = g;
+    gg.k = k;
+    hipLaunchKernelGGL(k_lr_qr_keep, dim3(sb.n), dim3(1024), lds, s, sb, gg, l);
+  }
+  void rl_move(int k) {
+    SGeo gg = g;
+    gg.k = k;
+    hipLaunchKernelGGL(k_rl_qr, dim3(sb.n), dim3(1024), lds, s, sb, gg, l);
+  }
+};
+
+}  // namespace
+
+// residual helpers implemented with the public dot entry points
+extern "C" int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qtt_mps* b, qtt_mps* x,
+                                 const qtt_solve_opts* opts, qtt_solve_info* info, void* stream);
+
+namespace qtt_solver_detail {
+// Declared in api.hip: workspace access for the solver.
+double* solver_ws(qtt_ctx* ctx, size_t doubles, int* rc);
+int* solver_iws(qtt_ctx* ctx, size_t ints, int* rc);
+int set_error(qtt_ctx* ctx, int code, const char* msg);
+int lds_of(qtt_ctx* ctx);
+double* pinned(qtt_ctx* ctx, size_t doubles, int* rc);
+}
+
+namespace qtt_solver_detail {
+hipError_t solver_init(int lds) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_rl_qr, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_lr_qr_keep, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  return e;
+}
+}
+
+extern "C" int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qtt_mps* b, qtt_mps* x,
+                                 const qtt_solve_opts* opts, qtt_solve_info* info, void* stream) {
+  using namespace qtt_solver_detail;
+  if (!ctx) return QTT_EINVAL;
+  if (n < 1 || !A || !b || !x || !opts) return set_error(ctx, QTT_EINVAL, "solve: bad arguments");
+  if (opts->contract_dt < QTT_F64 || opts->contract_dt > QTT_BF16 || opts->max_sweeps < 0 || opts->max_local_iters < 0)
+    return set_error(ctx, QTT_EINVAL, "solve: bad options");
+  const int L = x[0].L, cx = x[0].cap, cb = b[0].cap, wcap = A[0].wcap;
+  int W = 1;
+  for (int i = 0; i < n; ++i) {
+    if (!x[i].data || !x[i].bond || !b[i].data || !b[i].bond || !A[i].data || !A[i].bond || !A[i].bond_host)
+      return set_error(ctx, QTT_EINVAL, "solve: null pointer");
+    if (x[i].L != L || b[i].L != L || A[i].L != L || x[i].cap != cx || b[i].cap != cb || A[i].wcap != wcap ||
+        x[i].d != 2 || b[i].d != 2)
+      return set_error(ctx, QTT_ESHAPE, "solve: problems must share L, d and capacities");
+    for (int k = 0; k <= L; ++k) W = std::max(W, A[i].bond_host[k]);
+  }
+  if (L < 2 || cx > 256 || cb > 512 || W > wcap) return set_error(ctx, QTT_ESHAPE, "solve: unsupported sizes");
+  hipStream_t s = (hipStream_t)stream;
+  const SLay lay = SLay::make(L, cx, cx, cb, W);
+  int rc = 0;
+  double* ws = solver_ws(ctx, lay.total * std::min(n, GB), &rc);
+  if (rc) return rc;
+  int* iws = solver_iws(ctx, 128 * std::min(n, GB), &rc);
+  if (rc) return rc;
+  const int lds = lds_of(ctx);
+  int status = QTT_OK;
+  for (int i0 = 0; i0 < n; i0 += GB) {
+    Solver S;
+    S.sb.n = std::min(GB, n - i0);
+    for (int i = 0; i < S.sb.n; ++i) {
+      SChain& c = S.sb.c[i];
+      c.A = A[i0 + i].data; c.ab = A[i0 + i].bond;
+      c.b = b[i0 + i].data; c.bb = b[i0 + i].bond;
+      c.x = x[i0 + i].data; c.xb = x[i0 + i].bond;
+      c.kx = c.x; c.kxb = c.xb;
+      c.ws = ws + lay.total * i;
+      c.iws = iws + 128 * i;
+    }
+    S.g = SGeo{L, 0, cx, cb, wcap, W, cx, opts->local_tol, opts->max_local_iters, lds};
+    S.l = lay;
+    S.mode = opts->contract_dt;
+    S.s = s;
+    S.lds = lds;
+    S.flags = nullptr;
+    hipLaunchKernelGGL(k_transposes, dim3(L, S.sb.n), dim3(256), 0, s, S.sb, S.g, lay);
+    hipLaunchKernelGGL(k_mpo_ata, dim3(L, S.sb.n), dim3(256), 0, s, S.sb, S.g, lay);
+    hipLaunchKernelGGL(k_env_init, dim3(S.sb.n), dim3(64), 0, s, S.sb, S.g, lay);
+    // right-canonical start (bond structure kept), right environments
+    for (int k = L - 1; k >= 1; --k) S.rl_move(k);
+    for (int k = L - 1; k >= 1; --k) { S.ra_update(k); S.rb_update(k); }
+
+    // residual ||Ax - b|| / ||b|| via <x, A^T A x> - 2 <b, A x> + <b, b> (FP64)
+    auto residual = [&](double* out) -> int {
+      const int m = S.sb.n;
+      std::vector<qtt_mps> xs(m), bs(m);
+      std::vector<qtt_mpo> As(m), A2s(m);
+      std::vector<std::vector<int>> a2h(m);
+      for (int i = 0; i < m; ++i) {
+        xs[i] = x[i0 + i]; bs[i] = b[i0 + i]; As[i] = A[i0 + i];
+        a2h[i].resize(L + 1);
+        for (int k = 0; k <= L; ++k) a2h[i][k] = A[i0 + i].bond_host[k] * A[i0 + i].bond_host[k];
+        A2s[i].L = L; A2s[i].wcap = W * W; A2s[i].bond_host = a2h[i].data();
+        A2s[i].bond = S.sb.c[i].iws; A2s[i].data = S.sb.c[i].ws + lay.A2;
+      }
+      std::vector<double> xax(m), bax(m), bb(m);
+      int r2;
+      if ((r2 = qtt_dot_mpo(ctx, m, xs.data(), A2s.data(), xs.data(), xax.data(), stream))) return r2;
+      if ((r2 = qtt_dot_mpo(ctx, m, bs.data(), As.data(), xs.data(), bax.data(), stream))) return r2;
+      if ((r2 = qtt_dot(ctx, m, bs.data(), bs.data(), bb.data(), stream))) return r2;
+      for (int i = 0; i < m; ++i) {
+        const double r2v = xax[i] - 2.0 * bax[i] + bb[i];
+        out[i] = bb[i] > 0 ? std::sqrt(std::max(r2v, 0.0) / bb[i]) : 0.0;
+      }
+      return QTT_OK;
+    };
+    double res[GB], best[GB];
+    if ((rc = residual(res))) return rc;
+    for (int i = 0; i < S.sb.n; ++i) {
+      best[i] = res[i];
+      if (info) { info[i0 + i].residual0 = res[i]; info[i0 + i].residual = res[i]; info[i0 + i].sweeps = 0; }
+    }
+    int sweeps = 0;
+    bool all_done = true;
+    for (int i = 0; i < S.sb.n; ++i) all_done = all_done && res[i] <= opts->tol;
+    while (!all_done && sweeps < opts->max_sweeps) {
+      S.flags = pinned(ctx, 8 * (size_t)n, &rc);
+      if (rc) return rc;
+      // left-to-right half sweep
+      for (int k = 0; k < L; ++k) {
+        S.local_solve(k, S.mode);
+        if (k < L - 1) {
+          S.lr_move(k);
+          S.la_update(k);
+          S.lb_update(k);
+        }
+      }
+      // right-to-left half sweep
+      for (int k = L - 1; k >= 1; --k) {
+        S.rl_move(k);
+        S.ra_update(k);
+        S.rb_update(k);
+        S.local_solve(k - 1, S.mode);
+      }
+      ++sweeps;
+      if ((rc = residual(res))) return rc;
+      all_done = true;
+      bool improving = false;
+      for (int i = 0; i < S.sb.n; ++i) {
+        all_done = all_done && res[i] <= opts->tol;
+        if (res[i] < 0.9 * best[i]) improving = true;
+        best[i] = std::min(best[i], res[i]);
+        if (info) { info[i0 + i].residual = res[i]; info[i0 + i].sweeps = sweeps; }
+      }
+      if (!improving) break;   // stagnated at the bond-limited floor
+    }
+    // total local iterations
+    double* pin = pinned(ctx, 8 * (size_t)n, &rc);
+    if (rc) return rc;
+    for (int i = 0; i < S.sb.n; ++i)
+      if (hipMemcpyAsync(pin + i, S.sb.c[i].ws + lay.sc + S_ITERS_TOTAL, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return set_error(ctx, QTT_EHIP, "solve: copy of counters failed");
+    if (hipStreamSynchronize(s) != hipSuccess) return set_error(ctx, QTT_EHIP, "solve: stream sync failed");
+    for (int i = 0; i < S.sb.n; ++i) {
+      if (info) info[i0 + i].local_iters = (int)pin[i];
+      if (!std::isfinite(res[i])) status = QTT_ENUMERIC;
+      else if (res[i] > opts->tol && status == QTT_OK) status = QTT_ENOTCONVERGED;
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(ctx, QTT_EHIP, hipGetErrorString(e));
+  if (status == QTT_ENOTCONVERGED) set_error(ctx, QTT_ENOTCONVERGED, "solve: tolerance not reached");
+  return status;
+}
+
+// ---------------------------------------------------------------------------
+// variational fitting of y ~ M x (single-site, fixed bonds): each site update is
+// the exact projection of M x onto the orthonormal frame of the other cores of y,
+// so ||y - M x|| decreases monotonically (the variational mat-vec of Sec. 2.2).
+// y must be right-canonical on entry and is right-canonical on exit.
+// ---------------------------------------------------------------------------
+namespace qtt_solver_detail {
+int fit_sweeps(qtt_ctx* ctx, int n, const qtt_mpo* M, const qtt_mps* x, qtt_mps* y, int sweeps, int mode,
+               void* stream) {
+  if (sweeps <= 0) return QTT_OK;
+  const int L = x[0].L, cx = y[0].cap, ck = x[0].cap, wcap = M[0].wcap;
+  int W = 1;
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k <= L; ++k) W = std::max(W, M[i].bond_host[k]);
+  hipStream_t s = (hipStream_t)stream;
+  const SLay lay = SLay::make(L, cx, ck, 1, W);
+  int rc = 0;
+  double* ws = solver_ws(ctx, lay.total * std::min(n, GB), &rc);
+  if (rc) return rc;
+  for (int i0 = 0; i0 < n; i0 += GB) {
+    Solver S;
+    S.sb.n = std::min(GB, n - i0);
+    for (int i = 0; i < S.sb.n; ++i) {
+      SChain& c = S.sb.c[i];
+      std::memset(&c, 0, sizeof(c));
+      c.A = M[i0 + i].data; c.ab = M[i0 + i].bond;
+      c.x = y[i0 + i].data; c.xb = y[i0 + i].bond;
+      c.kx = x[i0 + i].data; c.kxb = x[i0 + i].bond;
+      c.ws = ws + lay.total * i;
+    }
+    S.g = SGeo{L, 0, cx, 1, wcap, W, ck, 0.0, 0, lds_of(ctx)};
+    S.l = lay;
+    S.mode = mode;
+    S.s = s;
+    S.lds = lds_of(ctx);
+    S.flags = nullptr;
+    hipLaunchKernelGGL(k_transposes, dim3(L, S.sb.n), dim3(256), 0, s, S.sb, S.g, lay);
+    hipLaunchKernelGGL(k_env_init, dim3(S.sb.n), dim3(64), 0, s, S.sb, S.g, lay);
+    for (int k = L - 1; k >= 1; --k) S.ra_update(k, mode);
+    for (int sw = 0; sw < sweeps; ++sw) {
+      for (int k = 0; k <= L - 2; ++k) {
+        S.project(k, mode);
+        S.lr_move(k);
+        S.la_step3(k, mode);
+      }
+      for (int k = L - 1; k >= 1; --k) {
+        S.project(k, mode);
+        S.rl_move(k);
+        S.ra_update(k, mode);
+      }
+    }
+    S.project(0, mode);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(ctx, QTT_EHIP, hipGetErrorString(e));
+  return QTT_OK;
+}
+}  // namespace qtt_solver_detail

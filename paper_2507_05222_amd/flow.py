@@ -1,0 +1,68 @@
+"""Flow-level helpers of the binding: build the cylinder operators with the
+library's host builder, hold the GPU state (u, v, p) and call the fractional step.
+Marshalling only; all arithmetic runs in libqtt.so."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import qtt as Q
+
+
+class FlowOps:
+    """Operators (MPOs) and boundary vectors of a 2^n x 2^n O-grid (Sec. 3.2.3)."""
+
+    def __init__(self, n, r_out=20.0, Re=100.0, dt=1e-3, alpha=0.0, u_inf=1.0, device="cuda"):
+        self.n, self.L = n, 2 * n
+        self.cyl = Q.cylinder(n, r_out, Re, dt, alpha, u_inf)
+        self.mpo = {k: Q.build_mpo(self.cyl, Q.OP[k], device) for k in
+                    ("DX", "DZ", "DXP", "DZP", "WX", "WZ", "HS", "P", "JH", "JMH")}
+        caps = [Q.build_host(self.cyl, Q.VEC[k])[2] for k in
+                ("BX_U", "BZ_U", "BX_V", "BZ_V", "BL_U", "BL_V", "BW")]
+        self.bc_cap = max(caps)
+        self.vec = {k: Q.build_vec(self.cyl, Q.VEC[k], self.bc_cap, device) for k in
+                    ("BX_U", "BZ_U", "BX_V", "BZ_V", "BL_U", "BL_V", "BW")}
+        m, v = self.mpo, self.vec
+        self.c = Q.CFlowOps(m["DX"].desc(), m["DZ"].desc(), m["DXP"].desc(), m["DZP"].desc(), m["WX"].desc(),
+                            m["WZ"].desc(), m["HS"].desc(), m["P"].desc(), m["JH"].desc(), m["JMH"].desc(),
+                            v["BX_U"].desc(), v["BZ_U"].desc(), v["BX_V"].desc(), v["BZ_V"].desc(),
+                            v["BL_U"].desc(), v["BL_V"].desc(), v["BW"].desc())
+
+    def bonds(self):
+        return {k: int(max(m.bond_host)) for k, m in self.mpo.items()}
+
+
+class FlowState:
+    def __init__(self, u: Q.MPS, v: Q.MPS, p: Q.MPS):
+        self.u, self.v, self.p = u, v, p
+
+    def c(self):
+        return Q.CFlowState(self.u.desc(), self.v.desc(), self.p.desc())
+
+
+def step_opts(dt, tol=1e-8, chi=64, dtype="f64", helm=None, pois=None, fit=2) -> Q.CStepOpts:
+    helm = helm or Q.solve_opts(tol=1e-10, max_sweeps=4, max_local_iters=60, local_tol=1e-6, dtype=dtype)
+    pois = pois or Q.solve_opts(tol=1e-8, max_sweeps=8, max_local_iters=200, local_tol=1e-4, dtype=dtype)
+    return Q.CStepOpts(float(dt), Q.CTrunc(float(tol), int(chi), int(fit)), Q.DTYPES.get(dtype, dtype), helm, pois)
+
+
+def fractional_step(ctx: Q.Context, ops: FlowOps, st: FlowState, opts: Q.CStepOpts, stream=None):
+    cs = st.c()
+    info = Q.CStepInfo()
+    ctx.check(Q.lib().qtt_fractional_step(ctx.h, ctypes.byref(ops.c), ctypes.byref(cs), ctypes.byref(opts),
+                                          ctypes.byref(info), Q._stream(stream)))
+    return info
+
+
+def grid_to_qtt_order(field: np.ndarray) -> np.ndarray:
+    """(2^n, 2^n) grid array -> dense vector in the interleaved MSB-first order of the library."""
+    N = field.shape[0]
+    n = int(np.log2(N))
+    i, j = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    q = np.zeros_like(i)
+    for m in range(n):
+        q = (q << 2) | (((i >> (n - 1 - m)) & 1) << 1) | ((j >> (n - 1 - m)) & 1)
+    out = np.empty(N * N)
+    out[q.ravel()] = field.ravel()
+    return out

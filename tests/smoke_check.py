@@ -1,0 +1,61 @@
+"""One small fractional step of the HIP path on cuda:0 checked against the CPU
+oracle (2^5 x 2^5 O-grid, Re = 100, dt = 1e-3, full-rank bonds so that the TT
+step reproduces the FD step up to solver tolerance). Test infrastructure."""
+import numpy as np
+
+from oracle import diag, fd, qttref as R
+from oracle.grid import OGrid
+from qtt_inputs import noise_fields, random_mps_cores
+
+
+def c1_initial(n=5, chi=8, tol=1e-10):
+    """Uniform flow plus seed-0 Gaussian noise (sigma 1e-3), compressed by the
+    library's TT-SVD at (tol, chi); returns dense grid fields and QTT-order vectors."""
+    from paper_2507_05222_amd import qtt as Q
+    L = 2 * n
+    nz = noise_fields(n, n, 1e-3, seed=0)
+    perm = R.grid_perm(n, n)
+    out = []
+    for f in (1.0 + nz[0], nz[1]):
+        m = Q.tt_svd_host(f.ravel()[perm], L, tol, chi, chi)
+        q = R.tt_full(m.cores())
+        grid = np.empty(4 ** n)
+        grid[perm] = q
+        out.append((grid, m))
+    return out
+
+
+def run_c1(cap=32, n=5, Re=100.0, dt=1e-3, trunc_tol=1e-13, dtype="f64"):
+    from paper_2507_05222_amd import flow as F, qtt as Q
+    L = 2 * n
+    ctx = Q.Context(0)
+    (u0, mu), (v0, mv) = c1_initial(n)
+    ops = F.FlowOps(n, 20.0, Re, dt)
+    u = Q.MPS(L, cap); v = Q.MPS(L, cap)
+    Q.add(ctx, 1.0, [mu], 0.0, [mu], [u], tol=0.0, chi=cap)
+    Q.add(ctx, 1.0, [mv], 0.0, [mv], [v], tol=0.0, chi=cap)
+    p = Q.MPS.from_cores(random_mps_cores(L, cap, seed=0), cap)
+    st = F.FlowState(u, v, p)
+    helm = Q.solve_opts(tol=1e-11, max_sweeps=2, max_local_iters=400, local_tol=1e-13, dtype=dtype)
+    pois = Q.solve_opts(tol=1e-10, max_sweeps=2, max_local_iters=3000, local_tol=1e-13, dtype=dtype)
+    info = F.fractional_step(ctx, ops, st, F.step_opts(dt, tol=trunc_tol, chi=cap, dtype=dtype, helm=helm, pois=pois))
+    g = OGrid(n, n)
+    S = fd.FDSolver(g, Re, dt)
+    ref = S.step(u0, v0, return_stages=True)
+    perm = R.grid_perm(n, n)
+    res = {}
+    for name, m in (("u", st.u), ("v", st.v), ("p", st.p)):
+        q = R.tt_full(m.cores())
+        grid = np.empty(4 ** n)
+        grid[perm] = q
+        res[name] = diag.eps_l2(g, grid, ref[name])
+    return res, info
+
+
+def run():
+    res, info = run_c1()
+    print("smoke: eps_L2 vs oracle", {k: f"{v:.2e}" for k, v in res.items()},
+          "poisson residual", f"{info.poisson.residual:.2e}", flush=True)
+    bad = {k: v for k, v in res.items() if not v < 1e-6}
+    if bad:
+        raise AssertionError(f"HIP fractional step disagrees with the oracle: {bad}")

@@ -1,0 +1,161 @@
+"""GPU parity of the TT algebra (apply, round, add, dot, local scaling) against the
+dense-vector oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import qttref as R
+from qtt_inputs import random_mpo_cores, random_mps_cores
+from tests.gpu_util import rel, right_orthonormal_error
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Q():
+    from paper_2507_05222_amd import qtt
+    return qtt
+
+
+@pytest.fixture(scope="module")
+def ctx(Q):
+    return Q.Context(0)
+
+
+def _rc(Q, ctx, cores, cap):
+    """Upload and right-canonicalise (exact rounding on the GPU)."""
+    x = Q.MPS.from_cores(cores, cap)
+    Q.round_(ctx, [x], tol=0.0, chi=cap)
+    return x
+
+
+@pytest.mark.parametrize("L,chi,w", [(8, 4, 3), (10, 8, 5)])
+def test_apply_exact(Q, ctx, L, chi, w):
+    xc = random_mps_cores(L, chi, seed=1)
+    M = random_mpo_cores(L, w, seed=2)
+    x = _rc(Q, ctx, xc, chi)
+    y = Q.MPS(L, chi * w)
+    Q.apply_mpo(ctx, [Q.MPO.from_cores(M)], [x], [y], tol=0.0, chi=chi * w)
+    ref = R.mpo_apply_dense(M, R.tt_full(xc))
+    yc = y.cores()
+    assert rel(R.tt_full(yc), ref) < 1e-10
+    assert right_orthonormal_error(yc) < 1e-10
+
+
+@pytest.mark.parametrize("dtype,bound", [("f32", 2e-5), ("bf16", 4e-2)])
+def test_apply_low_precision(Q, ctx, dtype, bound):
+    L, chi, w = 10, 8, 4
+    xc = random_mps_cores(L, chi, seed=3)
+    M = random_mpo_cores(L, w, seed=4)
+    x = _rc(Q, ctx, xc, chi)
+    y = Q.MPS(L, chi * w)
+    Q.apply_mpo(ctx, [Q.MPO.from_cores(M)], [x], [y], tol=0.0, chi=chi * w, dtype=dtype)
+    ref = R.mpo_apply_dense(M, R.tt_full(xc))
+    err = rel(R.tt_full(y.cores()), ref)
+    assert err < bound, err
+    assert right_orthonormal_error(y.cores()) < 1e-10   # truncation stays FP64
+
+
+def test_apply_multi_tile_ragged_exact(Q, ctx):
+    """Several GEMM tiles and a ragged tail: L=14, chi_x = 40, w = 2, so the exact
+    product has bonds up to 80 (64 + 16) and fits the output capacity."""
+    L, chi, w = 14, 40, 2
+    xc = random_mps_cores(L, chi, seed=5)
+    M = random_mpo_cores(L, w, seed=6)
+    x = _rc(Q, ctx, xc, chi)
+    y = Q.MPS(L, chi * w)
+    Q.apply_mpo(ctx, [Q.MPO.from_cores(M)], [x], [y], tol=0.0, chi=chi * w)
+    ref = R.mpo_apply_dense(M, R.tt_full(xc))
+    assert rel(R.tt_full(y.cores()), ref) < 1e-9
+    assert right_orthonormal_error(y.cores()) < 1e-9
+
+
+def test_apply_truncated_smooth_field(Q, ctx):
+    """Curvilinear d/dx of a smooth field, truncated: error within 2x of TT-SVD of the exact result."""
+    n = 6
+    L = 2 * n
+    from oracle.grid import OGrid
+    g = OGrid(n, n)
+    X = g.x_ext[2:-2]; Z = g.z_ext[2:-2]
+    f = np.exp(-0.05 * (X ** 2 + Z ** 2)) * np.sin(0.7 * X) + 0.3 * np.cos(0.4 * Z)
+    perm = R.grid_perm(n, n)
+    fv = f.ravel()[perm]
+    x = Q.tt_svd_host(fv, L, 1e-12, 64, 64)
+    Q.round_(ctx, [x], tol=0.0, chi=64)
+    D = Q.build_mpo(Q.cylinder(n), Q.OP["DX"])
+    ref = R.mpo_apply_dense(D.cores(), R.tt_full(x.cores()))
+    for chi in (8, 16):
+        y = Q.MPS(L, 64)
+        Q.apply_mpo(ctx, [D], [x], [y], tol=0.0, chi=chi)
+        err = rel(R.tt_full(y.cores()), ref)
+        opt = rel(R.tt_full(R.tt_svd(ref, L, chi_max=chi)), ref)
+        assert err <= 2.0 * opt + 1e-12, (chi, err, opt)
+        assert max(y.bonds()) <= chi
+
+
+def test_apply_batched_matches_single(Q, ctx):
+    L = 10
+    xs = [random_mps_cores(L, 6, seed=10 + i) for i in range(3)]
+    Ms = [random_mpo_cores(L, 2 + i, seed=20 + i) for i in range(3)]
+    X = [_rc(Q, ctx, c, 6) for c in xs]
+    Y = [Q.MPS(L, 24) for _ in range(3)]
+    # different MPO bonds inside one batch share one slot capacity
+    mpos = [Q.MPO.from_cores(m, wcap=4) for m in Ms]
+    Q.apply_mpo(ctx, mpos, X, Y, tol=0.0, chi=24)
+    for i in range(3):
+        ref = R.mpo_apply_dense(Ms[i], R.tt_full(xs[i]))
+        assert rel(R.tt_full(Y[i].cores()), ref) < 1e-10
+
+
+@pytest.mark.parametrize("tol", [1e-1, 1e-4, 1e-8])
+def test_round_error_bound(Q, ctx, tol):
+    L = 12
+    v = R.tt_full(random_mps_cores(L, 16, seed=7)) + 1e-5 * np.random.default_rng(0).standard_normal(2 ** L)
+    full = R.tt_svd(v, L)                      # exact TT of v (bonds up to 64)
+    x = Q.MPS.from_cores(full, 64)
+    Q.round_(ctx, [x], tol=tol, chi=64)
+    err = rel(R.tt_full(x.cores()), v)
+    assert err <= tol * (1 + 1e-8), err
+    assert right_orthonormal_error(x.cores()) < 1e-10
+
+
+def test_round_removes_redundancy(Q, ctx):
+    L = 10
+    xc = random_mps_cores(L, 8, seed=8)
+    z = Q.MPS(L, 16)
+    x = Q.MPS.from_cores(xc, 8)
+    Q.add(ctx, 1.0, [x], 1.0, [x], [z], tol=1e-12, chi=16)
+    assert max(z.bonds()) <= 8
+    assert rel(R.tt_full(z.cores()), 2 * R.tt_full(xc)) < 1e-11
+
+
+def test_add(Q, ctx):
+    L = 10
+    xc, yc = random_mps_cores(L, 8, seed=11), random_mps_cores(L, 5, seed=12)
+    z = Q.MPS(L, 13)
+    Q.add(ctx, 0.7, [Q.MPS.from_cores(xc, 8)], -1.3, [Q.MPS.from_cores(yc, 5)], [z], tol=0.0, chi=13)
+    assert rel(R.tt_full(z.cores()), 0.7 * R.tt_full(xc) - 1.3 * R.tt_full(yc)) < 1e-12
+
+
+def test_dots(Q, ctx):
+    L = 10
+    xc, yc = random_mps_cores(L, 7, seed=13), random_mps_cores(L, 9, seed=14)
+    M = random_mpo_cores(L, 3, seed=15)
+    X, Y = Q.MPS.from_cores(xc, 7), Q.MPS.from_cores(yc, 9)
+    xv, yv = R.tt_full(xc), R.tt_full(yc)
+    d = Q.dot(ctx, [X], [Y])
+    assert abs(d[0] - xv @ yv) < 1e-12 * np.linalg.norm(xv) * np.linalg.norm(yv)
+    d2 = Q.dot(ctx, [Y, Y], [Y, Y])
+    assert abs(d2[1] - yv @ yv) < 1e-12 * (yv @ yv)
+    dm = Q.dot_mpo(ctx, [X], [Q.MPO.from_cores(M)], [Y])
+    ref = xv @ R.mpo_apply_dense(M, yv)
+    assert abs(dm[0] - ref) < 1e-11 * abs(ref) + 1e-12
+
+
+def test_apply_local(Q, ctx):
+    L = 10
+    xc = random_mps_cores(L, 6, seed=16)
+    rng = np.random.default_rng(17)
+    D = [rng.standard_normal((1, 2, 2, 1)) for _ in range(L)]
+    y = Q.MPS(L, 6)
+    Q.apply_local(ctx, [Q.MPO.from_cores(D)], [Q.MPS.from_cores(xc, 6)], [y])
+    assert rel(R.tt_full(y.cores()), R.mpo_apply_dense(D, R.tt_full(xc))) < 1e-13
