@@ -184,7 +184,9 @@ typedef struct {
 typedef struct {
   double dt;                /* time step                                          */
   qtt_trunc trunc;          /* truncation of every TT operation of the step       */
-  int32_t contract_dt;      /* qtt_dtype of applies, Hadamards and local matvecs  */
+  int32_t contract_dt;      /* qtt_dtype of the derivative, divergence and gradient
+                               applies (differences of nearly equal terms: FP32 or FP64) */
+  int32_t product_dt;       /* qtt_dtype of the convection (Hadamard) products    */
   qtt_solve_opts helmholtz; /* options of the two predictor solves                */
   qtt_solve_opts poisson;   /* options of the pressure solve                      */
 } qtt_step_opts;
@@ -205,6 +207,19 @@ typedef struct {
  * All seven boundary vectors must share one capacity. */
 int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_flow_state* state,
                         const qtt_step_opts* opts, qtt_step_info* info, void* stream);
+
+/* ---- measurement hook (not part of the method) ----------------------------
+ * While a kernel class is selected, every launch of that class is bracketed by
+ * HIP events on its stream, and its GEMM-type kernels add their algorithmic work
+ * (2 M N K flops and 8 (M K + K N + M N) bytes per product, with the actual bond
+ * dimensions) to device counters. Classes: 0 zip-up site contractions, 1 zip-up
+ * Gram products, 2 zip-up Jacobi factorisation, 3 zip-up carry projection,
+ * 4 right-to-left Jacobi SVD sites, 5 Householder QR/LQ moves, 6 environment /
+ * local-matvec / projection GEMMs, 7 local CG updates; -1 stops timing.
+ * qtt_timer_read synchronises the device and returns the number of timed
+ * launches, their summed duration (ms) and the counted work. */
+int qtt_timer_start(qtt_ctx* ctx, int kernel_class);
+int qtt_timer_read(qtt_ctx* ctx, int64_t* launches, double* ms, double* flops, double* bytes);
 
 /* ---- host-side operator construction (setup, FP64, no GPU) ----------------
  * Builds, on the host, the TT cores of the operators and boundary vectors of a

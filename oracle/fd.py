@@ -129,10 +129,10 @@ class CurvilinearOps:
     def pressure_op(self, A_ext):
         """Interior matrix with p_{-1,j} = p_{0,j} folded in and p_{N_eta,j} = 0."""
         A_int, A_wall, _ = self._split(A_ext)
-        Nx = self.g.N_xi
-        A_int = A_int.tolil()
-        A_int[:, 0:Nx] = A_int[:, 0:Nx] + A_wall
-        return A_int.tocsr()
+        Nx, n = self.g.N_xi, self.s.n_int
+        # E maps the wall value of column j to interior unknown (0, j)
+        E = sp.csr_matrix((np.ones(Nx), (np.arange(Nx), np.arange(Nx))), shape=(Nx, n))
+        return (A_int + A_wall @ E).tocsr()
 
 
 # ----------------------------------------------------------------------------
@@ -154,8 +154,10 @@ def velocity_bc(g: OGrid, alpha: float = 0.0, u_inf: float = 1.0):
 class FDSolver:
     """Dense-grid fractional step with sparse-LU solves (factorised once)."""
 
-    def __init__(self, g: OGrid, Re: float, dt: float, alpha: float = 0.0):
-        self.g, self.Re, self.dt, self.alpha = g, Re, dt, alpha
+    def __init__(self, g: OGrid, Re: float, dt: float, alpha: float = 0.0, solver: str = "lu"):
+        """solver: "lu" (sparse LU of the literal seven-term operators) or "fft" (the
+        independent closed-form FFT/Thomas solvers, which agree with LU to round-off)."""
+        self.g, self.Re, self.dt, self.alpha, self.solver = g, Re, dt, alpha, solver
         ops = self.ops = CurvilinearOps(g)
         self.Dx, self.bcx = ops.velocity_op(ops.Dx_ext)
         self.Dz, self.bcz = ops.velocity_op(ops.Dz_ext)
@@ -196,11 +198,18 @@ class FDSolver:
         conv_v = u * gr["gxv"] + v * gr["gzv"]
         rhs_u = u - dt * conv_u + (dt / Re) * self.bcL(b["u_wall"], b["u_out"])
         rhs_v = v - dt * conv_v + (dt / Re) * self.bcL(b["v_wall"], b["v_out"])
-        us = self.luH().solve(rhs_u)                     # Eq. (intermediate_vel_eq)
-        vs = self.luH().solve(rhs_v)
+        if self.solver == "fft":
+            us = fast_helmholtz(self.g, dt / Re, rhs_u)  # Eq. (intermediate_vel_eq)
+            vs = fast_helmholtz(self.g, dt / Re, rhs_v)
+        else:
+            us = self.luH().solve(rhs_u)                 # Eq. (intermediate_vel_eq)
+            vs = self.luH().solve(rhs_v)
         div = (self.Dx @ us + self.bcx(b["u_wall"], b["u_out"])
                + self.Dz @ vs + self.bcz(b["v_wall"], b["v_out"])) / dt
-        p = self.luP().solve(-self.ops.absJ * div)      # Eq. (Poisson), J-weighted
+        if self.solver == "fft":
+            p = fast_poisson(self.g, -self.ops.absJ * div)
+        else:
+            p = self.luP().solve(-self.ops.absJ * div)  # Eq. (Poisson), J-weighted
         un = us - dt * (self.Dx_p @ p)
         vn = vs - dt * (self.Dz_p @ p)
         if return_stages:

@@ -482,3 +482,38 @@ double* pinned(qtt_ctx* ctx, size_t doubles, int* rc) {
 }
 
 }  // namespace qtt_solver_detail
+
+// ---------------------------------------------------------------------------
+// measurement hook
+// ---------------------------------------------------------------------------
+extern "C" int qtt_timer_start(qtt_ctx* ctx, int kernel_class) {
+  if (!ctx) return QTT_EINVAL;
+  if (kernel_class < -1 || kernel_class >= KC_COUNT) return fail(ctx, QTT_EINVAL, "timer: bad kernel class");
+  qttk::Timer& t = qttk::timer();
+  if (!t.cnt) HIPCHK(ctx, hipMalloc(&t.cnt, 2 * sizeof(double)));
+  HIPCHK(ctx, hipDeviceSynchronize());
+  HIPCHK(ctx, hipMemset(t.cnt, 0, 2 * sizeof(double)));
+  t.used = 0;
+  t.kc = kernel_class;
+  return QTT_OK;
+}
+
+extern "C" int qtt_timer_read(qtt_ctx* ctx, int64_t* launches, double* ms, double* flops, double* bytes) {
+  if (!ctx || !launches || !ms || !flops || !bytes) return QTT_EINVAL;
+  qttk::Timer& t = qttk::timer();
+  HIPCHK(ctx, hipDeviceSynchronize());
+  double total = 0.0;
+  for (size_t i = 0; i + 1 < t.used; i += 2) {
+    float e = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&e, t.ev[i], t.ev[i + 1]));
+    total += e;
+  }
+  double c[2] = {0.0, 0.0};
+  if (t.cnt) HIPCHK(ctx, hipMemcpy(c, t.cnt, sizeof(c), hipMemcpyDeviceToHost));
+  *launches = (int64_t)(t.used / 2);
+  *ms = total;
+  *flops = c[0];
+  *bytes = c[1];
+  t.kc = -1;
+  return QTT_OK;
+}

@@ -141,10 +141,23 @@ __device__ __forceinline__ double wave_sum(double v) {
 // rotates n/2 disjoint column pairs, one pair per wavefront at a time. Stops
 // after a sweep without rotations (|x_p.x_q| <= tol sqrt(|x_p|^2 |x_q|^2)).
 __device__ void jacobi_cols(double* X, int m, int ldx, int n, double* V, int ldv, int* flag) {
+  __shared__ double fro2_s[16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int ne = n + (n & 1);
   const double tol = 4.0e-16 * sqrt((double)(m > 1 ? m : 1));
   if (n < 2) return;
+  // Columns whose squared norm is below (1e-15)^2 of the Frobenius norm squared
+  // (invariant under the rotations) are at round-off level: their inner products
+  // are noise, so they count as converged (otherwise the sweeps never stop).
+  double f = 0.0;
+  for (int j = wave; j < n; j += nw)
+    for (int i = lane; i < m; i += 64) { const double u = X[(long)j * ldx + i]; f += u * u; }
+  f = wave_sum(f);
+  if (lane == 0) fro2_s[wave] = f;
+  __syncthreads();
+  double fro2 = 0.0;
+  for (int w = 0; w < nw; ++w) fro2 += fro2_s[w];
+  const double tiny2 = 1e-30 * fro2 + 1e-300;
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (threadIdx.x == 0) *flag = 0;
     __syncthreads();
@@ -162,7 +175,7 @@ __device__ void jacobi_cols(double* X, int m, int ldx, int n, double* V, int ldv
           a += u * u; b += w * w; c += u * w;
         }
         a = wave_sum(a); b = wave_sum(b); c = wave_sum(c);
-        if (!(a > 1e-300) || !(b > 1e-300)) continue;
+        if (!(a > tiny2) || !(b > tiny2)) continue;
         if (fabs(c) <= tol * sqrt(a) * sqrt(b)) continue;
         const double zeta = (b - a) / (2.0 * c);
         const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));

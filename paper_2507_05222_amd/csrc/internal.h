@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <vector>
 
 #define QTT_BMAX 32      // chains per launch (kernel-argument job table)
 
@@ -37,7 +38,35 @@ struct Geo {
   int cap2;     // slot capacity of the second input (x2)
   int splits;   // split-K factor of the Gram products
   int lds;      // dynamic LDS budget (bytes) of the one-workgroup kernels
+  double* cnt;  // measurement counters (algorithmic flops, bytes) or null
 };
+
+// Kernel classes of the measurement hook (qtt_timer_start / qtt_timer_read).
+enum KClass {
+  KC_ZIP_CONTRACT = 0,  // zip-up site contractions (carry.X_k, M_k.T1)
+  KC_ZIP_GRAM = 1,      // Gram products of the zip-up
+  KC_ZIP_FACTOR = 2,    // Jacobi eigen-decomposition of the Gram matrix
+  KC_ZIP_CARRY = 3,     // carry projection U^T Theta
+  KC_RL_SVD = 4,        // right-to-left Jacobi SVD sweep sites
+  KC_LR_QR = 5,         // Householder QR / LQ gauge moves
+  KC_JOBS = 6,          // environment / local-matvec / projection GEMMs
+  KC_CG = 7,            // local CG vector updates
+  KC_COUNT = 8
+};
+
+namespace qttk {
+struct Timer {
+  int kc = -1;                   // active class, -1 = off
+  double* cnt = nullptr;         // device counters [flops, bytes]
+  std::vector<hipEvent_t> ev;    // begin/end pairs
+  size_t used = 0;
+};
+Timer& timer();
+// Records an event on s if class kc is being timed (call before and after a launch).
+void tmark(int kc, hipStream_t s);
+// Device counter pointer for a launch of class kc (null unless kc is being timed).
+inline double* tcount(int kc) { return timer().kc == kc ? timer().cnt : nullptr; }
+}  // namespace qttk
 
 // Workspace layout of one chain for the zip-up / sweeps (offsets in doubles).
 struct WsLayout {

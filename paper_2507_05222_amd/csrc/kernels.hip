@@ -32,12 +32,21 @@ __global__ void k_zip_init(Batch b, WsLayout wl) {
   if (threadIdx.x < SC_COUNT) c.ws[wl.scal + threadIdx.x] = 0.0;
 }
 
+// Algorithmic work of one GEMM job, added once per job when measuring.
+__device__ __forceinline__ void count_gemm(double* cnt, int M, int N, int K) {
+  if (cnt && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && M > 0 && N > 0 && K > 0) {
+    atomicAdd(cnt, 2.0 * M * N * K);
+    atomicAdd(cnt + 1, 8.0 * ((double)M * K + (double)K * N + (double)M * N));
+  }
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(256) k_zip_t1(Batch b, Geo g, WsLayout wl) {
   if (blockIdx.z >= b.n) return;
   Chain& c = b.c[blockIdx.z];
   const int k = g.k;
-  const int M = c.yb[k] * c.mb[k], K = c.xb[k], N = 2 * g.capx;
+  const int M = c.yb[k] * c.mb[k], K = c.xb[k], N = 2 * g.capx;   // columns (s, c) padded to cap
+  count_gemm(g.cnt, M, 2 * c.xb[k + 1], K);
   const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
   if (m0 >= M) return;
   View A{c.ws + wl.carry, g.capx, 1};
@@ -69,6 +78,7 @@ __global__ void __launch_bounds__(256) k_zip_t2(Batch b, Geo g, WsLayout wl) {
   if (ap >= c.yb[k]) return;
   const int w = c.mb[k], w2 = c.mb[k + 1];
   const int M = 2 * w2, K = 2 * w, N = g.capx;
+  count_gemm(g.cnt, M, c.xb[k + 1], K);
   const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
   if (m0 >= M) return;
   View A{c.ws + wl.mt + (size_t)k * (2 * g.W) * (2 * g.W), 2 * w, 1};
@@ -85,6 +95,7 @@ __global__ void __launch_bounds__(256) k_zip_gram(Batch b, Geo g, WsLayout wl) {
   const int k = g.k;
   const int M = 2 * c.yb[k], w2 = c.mb[k + 1];
   const int K = w2 * g.capx;
+  if (sp == 0) count_gemm(g.cnt, M, M, w2 * c.xb[k + 1]);
   const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
   if (m0 >= M || n0 >= M) return;
   int chunk = (K + wl.splits - 1) / wl.splits;
@@ -164,6 +175,7 @@ __global__ void __launch_bounds__(256) k_zip_carry(Batch b, Geo g, WsLayout wl) 
   const int k = g.k;
   const int r = c.yb[k + 1], m = 2 * c.yb[k], w2 = c.mb[k + 1];
   const int N = w2 * g.capx;
+  count_gemm(g.cnt, r, w2 * c.xb[k + 1], m);
   const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
   if (m0 >= r || n0 >= N) return;
   View A{c.y + (long)k * slot(g.capy, 2), 1, g.capy};
@@ -531,33 +543,53 @@ void mpo_transpose(const Batch& b, const Geo& g, hipStream_t s) {
 }
 
 void zip_t1(const Batch& b, const Geo& g, hipStream_t s) {
+  Geo gg = g;
+  gg.cnt = tcount(KC_ZIP_CONTRACT);
+  tmark(KC_ZIP_CONTRACT, s);
   dim3 grid(cdiv(2 * g.capx, TILE), cdiv(g.capy * g.W, TILE), b.n);
   const WsLayout wl = lay(g);
-  if (g.mode == 0) hipLaunchKernelGGL(k_zip_t1<0>, grid, dim3(256), 0, s, b, g, wl);
-  else if (g.mode == 1) hipLaunchKernelGGL(k_zip_t1<1>, grid, dim3(256), 0, s, b, g, wl);
-  else hipLaunchKernelGGL(k_zip_t1<2>, grid, dim3(256), 0, s, b, g, wl);
+  if (g.mode == 0) hipLaunchKernelGGL(k_zip_t1<0>, grid, dim3(256), 0, s, b, gg, wl);
+  else if (g.mode == 1) hipLaunchKernelGGL(k_zip_t1<1>, grid, dim3(256), 0, s, b, gg, wl);
+  else hipLaunchKernelGGL(k_zip_t1<2>, grid, dim3(256), 0, s, b, gg, wl);
+  tmark(KC_ZIP_CONTRACT, s);
 }
 
 void zip_t2(const Batch& b, const Geo& g, hipStream_t s) {
+  Geo gg = g;
+  gg.cnt = tcount(KC_ZIP_CONTRACT);
+  tmark(KC_ZIP_CONTRACT, s);
   dim3 grid(cdiv(g.capx, TILE), cdiv(2 * g.W, TILE), b.n * g.capy);
   const WsLayout wl = lay(g);
-  if (g.mode == 0) hipLaunchKernelGGL(k_zip_t2<0>, grid, dim3(256), 0, s, b, g, wl);
-  else if (g.mode == 1) hipLaunchKernelGGL(k_zip_t2<1>, grid, dim3(256), 0, s, b, g, wl);
-  else hipLaunchKernelGGL(k_zip_t2<2>, grid, dim3(256), 0, s, b, g, wl);
+  if (g.mode == 0) hipLaunchKernelGGL(k_zip_t2<0>, grid, dim3(256), 0, s, b, gg, wl);
+  else if (g.mode == 1) hipLaunchKernelGGL(k_zip_t2<1>, grid, dim3(256), 0, s, b, gg, wl);
+  else hipLaunchKernelGGL(k_zip_t2<2>, grid, dim3(256), 0, s, b, gg, wl);
+  tmark(KC_ZIP_CONTRACT, s);
 }
 
 void zip_gram(const Batch& b, const Geo& g, hipStream_t s) {
+  Geo gg = g;
+  gg.cnt = tcount(KC_ZIP_GRAM);
+  tmark(KC_ZIP_GRAM, s);
   dim3 grid(cdiv(2 * g.capy, TILE), cdiv(2 * g.capy, TILE), b.n * g.splits);
-  hipLaunchKernelGGL(k_zip_gram, grid, dim3(256), 0, s, b, g, lay(g));
+  hipLaunchKernelGGL(k_zip_gram, grid, dim3(256), 0, s, b, gg, lay(g));
+  tmark(KC_ZIP_GRAM, s);
 }
 
 void zip_factor(const Batch& b, const Geo& g, hipStream_t s) {
-  hipLaunchKernelGGL(k_zip_factor, dim3(b.n), dim3(FACT_THREADS), g.lds, s, b, g, lay(g));
+  Geo gg = g;
+  gg.cnt = tcount(KC_ZIP_FACTOR);
+  tmark(KC_ZIP_FACTOR, s);
+  hipLaunchKernelGGL(k_zip_factor, dim3(b.n), dim3(FACT_THREADS), g.lds, s, b, gg, lay(g));
+  tmark(KC_ZIP_FACTOR, s);
 }
 
 void zip_carry(const Batch& b, const Geo& g, hipStream_t s) {
+  Geo gg = g;
+  gg.cnt = tcount(KC_ZIP_CARRY);
+  tmark(KC_ZIP_CARRY, s);
   dim3 grid(cdiv(g.W * g.capx, TILE), cdiv(g.capy, TILE), b.n);
-  hipLaunchKernelGGL(k_zip_carry, grid, dim3(256), 0, s, b, g, lay(g));
+  hipLaunchKernelGGL(k_zip_carry, grid, dim3(256), 0, s, b, gg, lay(g));
+  tmark(KC_ZIP_CARRY, s);
 }
 
 void zip_last(const Batch& b, const Geo& g, hipStream_t s) {
@@ -565,7 +597,11 @@ void zip_last(const Batch& b, const Geo& g, hipStream_t s) {
 }
 
 void rl_svd_site(const Batch& b, const Geo& g, int from_tmp, hipStream_t s) {
-  hipLaunchKernelGGL(k_rl_svd, dim3(b.n), dim3(FACT_THREADS), g.lds, s, b, g, lay(g), from_tmp);
+  Geo gg = g;
+  gg.cnt = tcount(KC_RL_SVD);
+  tmark(KC_RL_SVD, s);
+  hipLaunchKernelGGL(k_rl_svd, dim3(b.n), dim3(FACT_THREADS), g.lds, s, b, gg, lay(g), from_tmp);
+  tmark(KC_RL_SVD, s);
 }
 
 void rl_finish(const Batch& b, const Geo& g, hipStream_t s) {
@@ -573,7 +609,11 @@ void rl_finish(const Batch& b, const Geo& g, hipStream_t s) {
 }
 
 void lr_qr_site(const Batch& b, const Geo& g, int from_tmp, hipStream_t s) {
-  hipLaunchKernelGGL(k_lr_qr, dim3(b.n), dim3(FACT_THREADS), g.lds, s, b, g, lay(g), from_tmp);
+  Geo gg = g;
+  gg.cnt = tcount(KC_LR_QR);
+  tmark(KC_LR_QR, s);
+  hipLaunchKernelGGL(k_lr_qr, dim3(b.n), dim3(FACT_THREADS), g.lds, s, b, gg, lay(g), from_tmp);
+  tmark(KC_LR_QR, s);
 }
 
 void lr_finish(const Batch& b, const Geo& g, hipStream_t s) {
@@ -616,4 +656,25 @@ void dot_finish(const Batch& b, const Geo& g, hipStream_t s) {
   hipLaunchKernelGGL(k_dot_finish, dim3(b.n), dim3(64), 0, s, b, lay(g));
 }
 
+}  // namespace qttk
+
+namespace qttk {
+Timer& timer() {
+  static Timer t;
+  return t;
+}
+void tmark(int kc, hipStream_t s) {
+  Timer& t = timer();
+  if (t.kc != kc) return;
+  if (t.used >= t.ev.size()) {
+    if (t.ev.size() >= (size_t)1 << 17) return;          // cap: later launches are not recorded
+    const size_t grow = t.ev.empty() ? 4096 : t.ev.size();
+    for (size_t i = 0; i < grow; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      t.ev.push_back(e);
+    }
+  }
+  (void)hipEventRecord(t.ev[t.used++], s);
+}
 }  // namespace qttk

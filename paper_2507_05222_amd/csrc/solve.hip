@@ -44,6 +44,7 @@ struct GemmJob {
 };
 struct GemmBatch {
   int n, maxb;
+  double* cnt;              // measurement counters or null
   GemmJob j[GB];
 };
 
@@ -55,6 +56,10 @@ __global__ void __launch_bounds__(256) k_gemm_jobs(GemmBatch gb) {
   if (j.skip && *j.skip != 0.0) return;
   if (bi >= ev(j.nb)) return;
   const int M = ev(j.M), N = ev(j.N), K = ev(j.K);
+  if (gb.cnt && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && M > 0 && N > 0 && K > 0) {
+    atomicAdd(gb.cnt, 2.0 * M * N * K);
+    atomicAdd(gb.cnt + 1, 8.0 * ((double)M * K + (double)K * N + (double)M * N));
+  }
   const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
   if (m0 >= M || n0 >= N) return;
   View A{j.A + (long)bi * ev(j.sa), ev(j.ars), ev(j.acs)};
@@ -64,11 +69,15 @@ __global__ void __launch_bounds__(256) k_gemm_jobs(GemmBatch gb) {
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-void run_jobs(const GemmBatch& gb, int maxM, int maxN, int mode, hipStream_t s) {
+void run_jobs(const GemmBatch& gb0, int maxM, int maxN, int mode, hipStream_t s) {
+  GemmBatch gb = gb0;
+  gb.cnt = qttk::tcount(KC_JOBS);
   dim3 grid(cdiv(maxN, TILE), cdiv(maxM, TILE), gb.n * gb.maxb);
+  qttk::tmark(KC_JOBS, s);
   if (mode == 0) hipLaunchKernelGGL(k_gemm_jobs<0>, grid, dim3(256), 0, s, gb);
   else if (mode == 1) hipLaunchKernelGGL(k_gemm_jobs<1>, grid, dim3(256), 0, s, gb);
   else hipLaunchKernelGGL(k_gemm_jobs<2>, grid, dim3(256), 0, s, gb);
+  qttk::tmark(KC_JOBS, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -614,24 +623,38 @@ struct Solver {
   // each chunk the host reads the per-chain convergence flags (one small copy) and
   // stops enqueuing once every chain has converged. Kernels of converged chains
   // exit at once, so the chunking changes the launch count, not the arithmetic.
+  // With a low-precision matvec (mmode != 0) the solve is restarted from the FP64
+  // residual r = b_eff - M_eff x a few times (iterative refinement): the MFMA
+  // products only have to reduce the error of each correction, while the residual
+  // that decides convergence is always exact to FP64.
   double* flags = nullptr;   // host pinned, GB entries
   void local_solve(int k, int mmode) {
     SGeo gg = g;
     gg.k = k;
     beff(k);
     hipLaunchKernelGGL(k_precond, dim3(8, sb.n), dim3(256), 0, s, sb, gg, l);
-    matvec(k, true, mmode);
-    hipLaunchKernelGGL(k_cg_init, dim3(sb.n), dim3(1024), 0, s, sb, gg, l);
+    const int reps = (mmode == 0) ? 1 : 4;
+    const int per = std::max(1, g.maxit / reps);
+    gg.maxit = per;
+    for (int rep = 0; rep < reps; ++rep) {
+      matvec(k, true, 0);
+      hipLaunchKernelGGL(k_cg_init, dim3(sb.n), dim3(1024), 0, s, sb, gg, l);
+      cg_iterations(gg, k, mmode, per);
+    }
+  }
+  void cg_iterations(const SGeo& gg, int k, int mmode, int maxit) {
     int it = 0, chunk = 4;
-    while (it < g.maxit) {
-      const int m = std::min(chunk, g.maxit - it);
+    while (it < maxit) {
+      const int m = std::min(chunk, maxit - it);
       for (int j = 0; j < m; ++j) {
         matvec(k, false, mmode);
+        qttk::tmark(KC_CG, s);
         hipLaunchKernelGGL(k_cg_step, dim3(sb.n), dim3(1024), 0, s, sb, gg, l);
+        qttk::tmark(KC_CG, s);
       }
       it += m;
       chunk = std::min(2 * chunk, 64);
-      if (it >= g.maxit || !flags) break;
+      if (it >= maxit || !flags) break;
       for (int i = 0; i < sb.n; ++i)
         (void)hipMemcpyAsync(flags + i, sb.c[i].ws + l.sc + S_DONE, sizeof(double), hipMemcpyDeviceToHost, s);
       (void)hipStreamSynchronize(s);
@@ -644,12 +667,16 @@ struct Solver {
   void lr_move(int k) {
     SGeo gg = g;
     gg.k = k;
+    qttk::tmark(KC_LR_QR, s);
     hipLaunchKernelGGL(k_lr_qr_keep, dim3(sb.n), dim3(1024), lds, s, sb, gg, l);
+    qttk::tmark(KC_LR_QR, s);
   }
   void rl_move(int k) {
     SGeo gg = g;
     gg.k = k;
+    qttk::tmark(KC_LR_QR, s);
     hipLaunchKernelGGL(k_rl_qr, dim3(sb.n), dim3(1024), lds, s, sb, gg, l);
+    qttk::tmark(KC_LR_QR, s);
   }
 };
 

@@ -34,6 +34,8 @@ extern "C" int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_fl
   using namespace qtt_solver_detail;
   if (!ctx) return QTT_EINVAL;
   if (!ops || !st || !o || !(o->dt > 0.0)) return set_error(ctx, QTT_EINVAL, "step: bad arguments");
+  if (o->contract_dt < QTT_F64 || o->contract_dt > QTT_BF16 || o->product_dt < QTT_F64 || o->product_dt > QTT_BF16)
+    return set_error(ctx, QTT_EINVAL, "step: bad dtype");
   const int L = st->u.L, cap = st->u.cap;
   if (st->v.L != L || st->p.L != L || st->v.cap != cap || !st->u.data || !st->v.data || !st->p.data)
     return set_error(ctx, QTT_ESHAPE, "step: u, v must share L and cap; p must share L");
@@ -86,7 +88,7 @@ extern "C" int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_fl
     qtt_mpo M[4] = {DU, DV, DU, DV};
     qtt_mps x[4] = {T[GXU], T[GZU], T[GXV], T[GZV]};
     qtt_mps y[4] = {T[H0], T[H1], T[H2], T[H3]};
-    if ((rc = qtt_apply_mpo(ctx, 4, M, x, y, tr, mode, stream))) return rc;
+    if ((rc = qtt_apply_mpo(ctx, 4, M, x, y, tr, o->product_dt, stream))) return rc;
     double one[2] = {1, 1};
     qtt_mps a2[2] = {T[H0], T[H2]}, b2[2] = {T[H1], T[H3]}, c2[2] = {T[CONVU], T[CONVV]};
     if ((rc = qtt_add(ctx, 2, one, a2, one, b2, c2, tr, stream))) return rc;
@@ -101,7 +103,21 @@ extern "C" int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_fl
     qtt_mpo jh[2] = {ops->Jh, ops->Jh};
     qtt_mps rs[2] = {T[RSU], T[RSV]}, w[2] = {T[WU], T[WV]};
     if ((rc = qtt_apply_local(ctx, 2, jh, rhs, rs, stream))) return rc;
-    if ((rc = qtt_apply_local(ctx, 2, jh, uv, w, stream))) return rc;      // initial guess |J|^(1/2) v^m
+    // initial guess w0 = |J|^(1/2) rhs (H = I + O(dt/Re)); it carries the bond
+    // structure of the right-hand side, which single-site updates cannot enlarge
+    {
+      Batch b;
+      b.n = 2;
+      std::memset(&b.c[0], 0, sizeof(Chain) * 2);
+      for (int i = 0; i < 2; ++i) {
+        b.c[i].x = rs[i].data; b.c[i].xb = rs[i].bond; b.c[i].y = w[i].data; b.c[i].yb = w[i].bond;
+        b.c[i].alpha = 1.0;
+      }
+      Geo g;
+      std::memset(&g, 0, sizeof(g));
+      g.L = L; g.capx = cap; g.capy = cap; g.d = 2;
+      qttk::copy_mps(b, g, s);
+    }
     qtt_mpo hs[2] = {ops->Hs, ops->Hs};
     qtt_solve_info hi[2];
     qtt_solve_opts ho = o->helmholtz;

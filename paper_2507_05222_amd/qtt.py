@@ -69,7 +69,7 @@ class CFlowState(ctypes.Structure):
 
 class CStepOpts(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("trunc", CTrunc), ("contract_dt", ctypes.c_int32),
-                ("helmholtz", CSolveOpts), ("poisson", CSolveOpts)]
+                ("product_dt", ctypes.c_int32), ("helmholtz", CSolveOpts), ("poisson", CSolveOpts)]
 
 
 class CStepInfo(ctypes.Structure):
@@ -107,6 +107,9 @@ def lib():
             L.qtt_poisson_solve.argtypes = [vp, i32, p(CMpo), p(CMps), p(CMps), p(CSolveOpts), p(CSolveInfo), vp]
         if hasattr(L, "qtt_fractional_step"):
             L.qtt_fractional_step.argtypes = [vp, p(CFlowOps), p(CFlowState), p(CStepOpts), p(CStepInfo), vp]
+        L.qtt_timer_start.argtypes = [vp, i32]
+        L.qtt_timer_read.argtypes = [vp, p(ctypes.c_int64), p(ctypes.c_double), p(ctypes.c_double),
+                                     p(ctypes.c_double)]
         L.qtt_build_host.argtypes = [p(CCylinder), i32, ctypes.c_int32, vp, vp, p(ctypes.c_int32)]
         L.qtt_tt_svd_host.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, p(CTrunc), ctypes.c_int32, vp, vp]
         _lib = L
@@ -350,3 +353,29 @@ def tt_svd_host(dense: np.ndarray, L: int, tol: float, chi: int, cap: int, devic
     if rc != 0:
         raise QttError(rc, "qtt_tt_svd_host")
     return MPS.from_slots(slots, bonds, cap, device)
+
+
+# ---------------------------------------------------------------------------
+# measurement hook
+# ---------------------------------------------------------------------------
+KERNEL_CLASSES = {"zip_contract": 0, "zip_gram": 1, "zip_factor": 2, "zip_carry": 3, "rl_svd": 4,
+                  "qr_moves": 5, "env_gemm": 6, "cg_update": 7}
+
+
+class KernelTimer:
+    """HIP-event timing of one kernel class inside the library (qtt_timer_*)."""
+
+    def __init__(self, ctx: Context, name: str, dtype: str = "f64"):
+        self.ctx, self.name, self.dtype = ctx, name, dtype
+        self.kc = KERNEL_CLASSES[name]
+
+    def start(self):
+        self.ctx.check(lib().qtt_timer_start(self.ctx.h, self.kc))
+
+    def read(self):
+        n = ctypes.c_int64(0)
+        ms, fl, by = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+        self.ctx.check(lib().qtt_timer_read(self.ctx.h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl),
+                                            ctypes.byref(by)))
+        return {"name": self.name, "dtype": self.dtype, "launches": int(n.value), "ms": ms.value,
+                "flops": fl.value, "bytes": by.value}

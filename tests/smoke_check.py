@@ -25,7 +25,8 @@ def c1_initial(n=5, chi=8, tol=1e-10):
     return out
 
 
-def run_c1(cap=32, n=5, Re=100.0, dt=1e-3, trunc_tol=1e-13, dtype="f64"):
+def run_c1(cap=32, n=5, Re=100.0, dt=1e-3, trunc_tol=1e-13, dtype="f64", helm_dtype=None, pois_dtype=None,
+           product_dtype=None):
     from paper_2507_05222_amd import flow as F, qtt as Q
     L = 2 * n
     ctx = Q.Context(0)
@@ -36,9 +37,10 @@ def run_c1(cap=32, n=5, Re=100.0, dt=1e-3, trunc_tol=1e-13, dtype="f64"):
     Q.add(ctx, 1.0, [mv], 0.0, [mv], [v], tol=0.0, chi=cap)
     p = Q.MPS.from_cores(random_mps_cores(L, cap, seed=0), cap)
     st = F.FlowState(u, v, p)
-    helm = Q.solve_opts(tol=1e-11, max_sweeps=2, max_local_iters=400, local_tol=1e-13, dtype=dtype)
-    pois = Q.solve_opts(tol=1e-10, max_sweeps=2, max_local_iters=3000, local_tol=1e-13, dtype=dtype)
-    info = F.fractional_step(ctx, ops, st, F.step_opts(dt, tol=trunc_tol, chi=cap, dtype=dtype, helm=helm, pois=pois))
+    helm = Q.solve_opts(tol=1e-11, max_sweeps=2, max_local_iters=400, local_tol=1e-13, dtype=helm_dtype or dtype)
+    pois = Q.solve_opts(tol=1e-10, max_sweeps=2, max_local_iters=3000, local_tol=1e-13, dtype=pois_dtype or dtype)
+    info = F.fractional_step(ctx, ops, st, F.step_opts(dt, tol=trunc_tol, chi=cap, dtype=dtype, helm=helm, pois=pois,
+                                                       product=product_dtype))
     g = OGrid(n, n)
     S = fd.FDSolver(g, Re, dt)
     ref = S.step(u0, v0, return_stages=True)

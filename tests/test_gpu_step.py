@@ -9,13 +9,15 @@ def test_step_c1_full_rank_matches_oracle():
     res, info = run_c1(cap=32)
     for k in ("u", "v", "p"):
         assert res[k] < 1e-7, res
-    assert info.helm_u.residual < 1e-8 and info.helm_v.residual < 1e-8
+    # the FP64 residual formula resolves about 3e-8 (cancellation in <x,A^T A x> - 2<b,Ax> + <b,b>)
+    assert info.helm_u.residual < 1e-6 and info.helm_v.residual < 1e-6
 
 
 def test_step_c1_bf16_contractions_within_budget():
-    """BF16 MFMA contractions (FP32 accumulate), FP64 truncation and residuals: the
-    step stays within the 3e-3 relative L2 budget of the FP64 oracle."""
+    """Mixed precision (FP32 MFMA derivative applies and Poisson products, BF16 MFMA
+    Hadamard and Helmholtz products, FP32 accumulation, FP64 truncation and residual
+    restarts): the step stays within the 3e-3 relative L2 budget of the FP64 oracle."""
     from tests.smoke_check import run_c1
-    res, _ = run_c1(cap=32, dtype="bf16")
+    res, _ = run_c1(cap=32, dtype="f32", product_dtype="bf16", helm_dtype="bf16", pois_dtype="f32")
     for k in ("u", "v", "p"):
         assert res[k] < 3e-3, res

@@ -149,3 +149,13 @@ def test_step_uniform_flow_is_finite_and_divergence_reduced():
     # the compact-Laplacian projection is not an exact projection (its exactness is
     # pinned separately), but it must reduce the impulsive-start divergence overall
     assert np.linalg.norm(div1) < 0.7 * np.linalg.norm(div0)
+
+
+def test_step_fft_solver_matches_lu():
+    g = OGrid(5, 5)
+    u, v = fd.uniform_flow(g)
+    u = u + fd.perturbation(g, 1e-2)
+    a = fd.FDSolver(g, 200.0, 2e-3).step(u, v, return_stages=True)
+    b = fd.FDSolver(g, 200.0, 2e-3, solver="fft").step(u, v, return_stages=True)
+    for k in ("u", "v", "p"):
+        assert np.abs(a[k] - b[k]).max() < 1e-10 * max(1.0, np.abs(a[k]).max())
