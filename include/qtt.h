@@ -83,20 +83,27 @@ typedef struct {
                            zip-up (Sec. 2.2), 0..64; other calls ignore it */
 } qtt_trunc;
 
-/* Options of the variational linear solve (Sec. 2.1.4, Eq. LSE). */
+/* Options of the variational linear solve (Sec. 2.1.4, Eq. LSE).
+ * Residual measure: before each local update the solver evaluates, in FP64,
+ * r_k = ||P_k (b - A x)|| with P_k the orthogonal projection onto the frame of
+ * site k (the residual of the local system). The "residual" of a sweep is the
+ * largest r_k / ||b|| met in it; all r_k vanish at a stationary point of the
+ * alternating iteration, and r_k <= ||b - A x|| always. */
 typedef struct {
-  double tol;               /* stop when ||Ax-b||/||b|| <= tol (FP64)             */
-  int32_t max_sweeps;       /* full sweeps (left-to-right + right-to-left)        */
+  double tol;               /* stop when the sweep residual is <= tol             */
+  int32_t max_sweeps;       /* full sweeps (left-to-right + right-to-left), >= 1  */
   int32_t max_local_iters;  /* CG iterations per local problem                    */
-  double local_tol;         /* relative residual target of each local problem     */
+  double local_tol;         /* local CG stops once its residual is below local_tol
+                               times the local residual before the update, or below
+                               tol * ||b|| / (2 sqrt(L))                          */
   int32_t contract_dt;      /* qtt_dtype of the local matrix-vector products      */
 } qtt_solve_opts;
 
 typedef struct {
   int32_t sweeps;           /* sweeps performed                                   */
   int32_t local_iters;      /* total CG iterations                                */
-  double residual;          /* final ||Ax-b||/||b|| (FP64)                        */
-  double residual0;         /* initial ||Ax0-b||/||b||                            */
+  double residual;          /* sweep residual of the last sweep (FP64)            */
+  double residual0;         /* sweep residual of the first sweep                  */
 } qtt_solve_info;
 
 /* ---- context ------------------------------------------------------------ */
@@ -147,13 +154,38 @@ int qtt_dot_mpo(qtt_ctx* ctx, int n, const qtt_mps* x, const qtt_mpo* A, const q
  * 2x2 matrix (w = 1). Exact (no truncation, bonds unchanged). */
 int qtt_apply_local(qtt_ctx* ctx, int n, const qtt_mpo* D, const qtt_mps* x, qtt_mps* y, void* stream);
 
+/* One term c M x of a variational fit; M == NULL means the identity. */
+typedef struct {
+  double coef;
+  const qtt_mpo* M;
+  const qtt_mps* x;
+} qtt_term;
+
+/* Variational fit y_i ~ sum_t c_it M_it x_it at fixed bonds (Sec. 2.2: the
+ * variational mat-vec / addition / elementwise product of Table 1). Single-site
+ * sweeps: each core of y becomes the projection of the sum onto the orthonormal
+ * frame of the other cores (environments of <y|M_t|x_t>, contractions on MFMA in
+ * contract_dt), the gauge moves by Householder QR/LQ; ||y - sum|| decreases
+ * monotonically. terms: n*nterms entries, problem-major (nterms <= 4); term t of
+ * every problem shares the ket capacity and the MPO wcap (or is the identity for
+ * every problem). init = 1 starts from a random train on the profile
+ * min(2^k, 2^(L-k), chi) (the first pass is then a randomized sketch of the sum);
+ * init = 0 starts from the current content of y, which must be right-canonical
+ * with bonds <= chi (e.g. the previous time step's result). sweeps (>= 1) full
+ * left-right-left sweeps; y ends right-canonical. No input may alias y. */
+int qtt_fit(qtt_ctx* ctx, int n, int nterms, const qtt_term* terms, qtt_mps* y, int chi, int sweeps,
+            int init, int contract_dt, void* stream);
+
 /* Single-site variational (ALS / one-site DMRG) solve of A x = b (Sec. 2.1.4,
  * Eq. LSE and its cost function; local problems by CG with the fast matvec of
  * App. G). A must be symmetric positive definite. On entry x holds the initial
  * guess (its bond structure is kept: single-site updates cannot grow bonds); on
- * exit the solution, right-canonical. info (HOST, n entries, may be NULL)
- * receives sweeps, CG iterations and FP64 residuals. Returns QTT_ENOTCONVERGED
- * if some problem stopped at max_sweeps above tol (x then holds its best iterate). */
+ * exit the solution, right-canonical. At least one sweep is made. Sweeps stop
+ * when every problem's sweep residual is <= tol, at max_sweeps, or when no
+ * problem improved its best sweep residual by 10% (after two sweeps). info
+ * (HOST, n entries, may be NULL) receives sweeps, CG iterations and the sweep
+ * residuals. Returns QTT_ENOTCONVERGED if some problem ended above tol (x then
+ * holds its last iterate). */
 int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qtt_mps* b, qtt_mps* x,
                       const qtt_solve_opts* opts, qtt_solve_info* info, void* stream);
 

@@ -13,6 +13,7 @@
 
 namespace qtt_solver_detail {
 hipError_t solver_init(int lds);
+hipError_t fit_init(int lds);
 int fit_sweeps(qtt_ctx* ctx, int n, const qtt_mpo* M, const qtt_mps* x, qtt_mps* y, int sweeps, int mode,
                void* stream);
 }
@@ -33,6 +34,10 @@ struct qtt_ctx {
   size_t siws_cap = 0;
   double* pool = nullptr;      // fractional-step temporaries (device)
   size_t pool_cap = 0;         // bytes
+  double* idm = nullptr;       // identity MPO cores (bond 1), for plain terms of a fit
+  int* idb = nullptr;          // its bonds (all ones)
+  int id_L = 0;
+  int step_warm_L = 0, step_warm_cap = 0;   // shape of the last completed fractional step
 };
 
 namespace {
@@ -70,6 +75,7 @@ int ensure_ws(qtt_ctx* ctx, size_t doubles) {
   }
   const size_t want = doubles + doubles / 4;
   HIPCHK(ctx, hipMalloc(&ctx->ws, want * sizeof(double)));
+  HIPCHK(ctx, hipMemset(ctx->ws, 0, want * sizeof(double)));   // padding entries must be finite
   ctx->ws_cap = want;
   return QTT_OK;
 }
@@ -83,6 +89,7 @@ int ensure_tmp(qtt_ctx* ctx, size_t bytes) {
   }
   const size_t want = bytes + bytes / 4;
   HIPCHK(ctx, hipMalloc(&ctx->tmp, want));
+  HIPCHK(ctx, hipMemset(ctx->tmp, 0, want));
   ctx->tmp_cap = want;
   return QTT_OK;
 }
@@ -191,6 +198,7 @@ int qtt_create(int device, qtt_ctx** out) {
   ctx->lds = std::max(16 * 1024, std::min(lds, 160 * 1024) - 16 * 1024);
   e = qttk::init(ctx->lds);
   if (e == hipSuccess) e = qtt_solver_detail::solver_init(ctx->lds);
+  if (e == hipSuccess) e = qtt_solver_detail::fit_init(ctx->lds);
   if (e != hipSuccess) { delete ctx; return QTT_EHIP; }
   *out = ctx;
   return QTT_OK;
@@ -206,6 +214,8 @@ void qtt_destroy(qtt_ctx* ctx) {
   if (ctx->sws) hipFree(ctx->sws);
   if (ctx->siws) hipFree(ctx->siws);
   if (ctx->pool) hipFree(ctx->pool);
+  if (ctx->idm) hipFree(ctx->idm);
+  if (ctx->idb) hipFree(ctx->idb);
   delete ctx;
 }
 
@@ -461,6 +471,7 @@ static T* grow(qtt_ctx* ctx, T*& buf, size_t& cap, size_t count, int* rc) {
   }
   const size_t want = count + count / 4;
   hipError_t e = hipMalloc(&buf, want * sizeof(T));
+  if (e == hipSuccess) e = hipMemset(buf, 0, want * sizeof(T));   // padding entries must be finite
   if (e != hipSuccess) { *rc = fail(ctx, QTT_EHIP, "hipMalloc(%zu): %s", want * sizeof(T), hipGetErrorString(e)); return nullptr; }
   cap = want;
   return buf;
@@ -475,6 +486,26 @@ double* step_pool(qtt_ctx* ctx, size_t doubles, int* rc) {
   return p;
 }
 int set_error(qtt_ctx* ctx, int code, const char* msg) { return fail(ctx, code, "%s", msg); }
+const double* identity_mpo(qtt_ctx* ctx, int L, const int** bond, int* rc) {
+  *rc = QTT_OK;
+  if (ctx->id_L < L) {
+    if (ctx->idm) { (void)hipDeviceSynchronize(); (void)hipFree(ctx->idm); (void)hipFree(ctx->idb); }
+    ctx->idm = nullptr; ctx->idb = nullptr; ctx->id_L = 0;
+    std::vector<double> cores((size_t)L * 4, 0.0);
+    for (int k = 0; k < L; ++k) { cores[4 * k + 0] = 1.0; cores[4 * k + 3] = 1.0; }   // [1][o][i][1] = delta(o, i)
+    std::vector<int> ones(L + 1, 1);
+    hipError_t e = hipMalloc(&ctx->idm, cores.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&ctx->idb, ones.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMemcpy(ctx->idm, cores.data(), cores.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->idb, ones.data(), ones.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { *rc = fail(ctx, QTT_EHIP, "identity MPO: %s", hipGetErrorString(e)); return nullptr; }
+    ctx->id_L = L;
+  }
+  *bond = ctx->idb;
+  return ctx->idm;
+}
+bool step_warm(qtt_ctx* ctx, int L, int cap) { return ctx->step_warm_L == L && ctx->step_warm_cap == cap; }
+void set_step_warm(qtt_ctx* ctx, int L, int cap) { ctx->step_warm_L = L; ctx->step_warm_cap = cap; }
 int lds_of(qtt_ctx* ctx) { return ctx->lds; }
 double* pinned(qtt_ctx* ctx, size_t doubles, int* rc) {
   *rc = ensure_pinned(ctx, doubles);

@@ -31,9 +31,9 @@ __host__ __device__ inline size_t align64(size_t x) { return (x + 63) & ~size_t(
 struct View { const double* p; long rs, cs; };
 
 template <int MODE> struct Cfg;
-template <> struct Cfg<0> { using T = double; using Acc = v4d; static constexpr int BK = 16; static constexpr int PAD = 1; };
-template <> struct Cfg<1> { using T = float;  using Acc = v4f; static constexpr int BK = 16; static constexpr int PAD = 1; };
-template <> struct Cfg<2> { using T = __bf16; using Acc = v4f; static constexpr int BK = 32; static constexpr int PAD = 8; };
+template <> struct Cfg<0> { using T = double; using Acc = v4d; static constexpr int BK = 32; static constexpr int PAD = 1; };
+template <> struct Cfg<1> { using T = float;  using Acc = v4f; static constexpr int BK = 32; static constexpr int PAD = 1; };
+template <> struct Cfg<2> { using T = __bf16; using Acc = v4f; static constexpr int BK = 64; static constexpr int PAD = 8; };
 
 template <int MODE>
 __device__ __forceinline__ typename Cfg<MODE>::T to_t(double v) {
@@ -41,6 +41,9 @@ __device__ __forceinline__ typename Cfg<MODE>::T to_t(double v) {
   else return (typename Cfg<MODE>::T)v;
 }
 
+// The K loop keeps the next K-block's global loads in flight (in registers)
+// while the MFMAs of the current block run from LDS: with the small grids of
+// the bond-dimension GEMMs the tile time is dominated by load latency.
 template <int MODE>
 __device__ void gemm_tile(int M, int N, int k0, int k1, View A, View B, double* C, long crs, long ccs,
                           double alpha, double beta, int m0, int n0) {
@@ -48,32 +51,50 @@ __device__ void gemm_tile(int M, int N, int k0, int k1, View A, View B, double* 
   using Acc = typename Cfg<MODE>::Acc;
   constexpr int BK = Cfg<MODE>::BK;
   constexpr int PAD = Cfg<MODE>::PAD;
+  constexpr int PER = TILE * BK / 256;     // elements of each operand per thread and K-block
   __shared__ __attribute__((aligned(16))) T As[TILE][BK + PAD];
   __shared__ __attribute__((aligned(16))) T Bs[TILE][BK + PAD];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
+  const bool a_kfast = (A.cs == 1), b_nfast = (B.cs == 1);
   Acc acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
-
-  for (int kb = k0; kb < k1; kb += BK) {
-    for (int e = tid; e < TILE * BK; e += 256) {
+  T ra[PER], rb[PER];
+  auto load = [&](int kb) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q;
       int i, kk;
-      if (A.cs == 1) { i = e / BK; kk = e % BK; } else { i = e % TILE; kk = e / TILE; }
+      if (a_kfast) { i = e / BK; kk = e % BK; } else { i = e % TILE; kk = e / TILE; }
       const int gm = m0 + i, gk = kb + kk;
-      const double v = (gm < M && gk < k1) ? A.p[(long)gm * A.rs + (long)gk * A.cs] : 0.0;
-      As[i][kk] = to_t<MODE>(v);
+      ra[q] = to_t<MODE>((gm < M && gk < k1) ? A.p[(long)gm * A.rs + (long)gk * A.cs] : 0.0);
+      int j;
+      if (b_nfast) { j = e % TILE; kk = e / TILE; } else { kk = e % BK; j = e / BK; }
+      const int gn = n0 + j;
+      const int gk2 = kb + kk;
+      rb[q] = to_t<MODE>((gn < N && gk2 < k1) ? B.p[(long)gk2 * B.rs + (long)gn * B.cs] : 0.0);
     }
-    for (int e = tid; e < TILE * BK; e += 256) {
-      int j, kk;
-      if (B.cs == 1) { j = e % TILE; kk = e / TILE; } else { kk = e % BK; j = e / BK; }
-      const int gn = n0 + j, gk = kb + kk;
-      const double v = (gn < N && gk < k1) ? B.p[(long)gk * B.rs + (long)gn * B.cs] : 0.0;
-      Bs[j][kk] = to_t<MODE>(v);
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q;
+      int i, kk;
+      if (a_kfast) { i = e / BK; kk = e % BK; } else { i = e % TILE; kk = e / TILE; }
+      As[i][kk] = ra[q];
+      int j;
+      if (b_nfast) { j = e % TILE; kk = e / TILE; } else { kk = e % BK; j = e / BK; }
+      Bs[j][kk] = rb[q];
     }
+  };
+  if (k0 < k1) load(k0);
+  for (int kb = k0; kb < k1; kb += BK) {
+    store();
     __syncthreads();
+    if (kb + BK < k1) load(kb + BK);
     if constexpr (MODE == 0) {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
@@ -95,14 +116,17 @@ __device__ void gemm_tile(int M, int N, int k0, int k1, View A, View B, double* 
         acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
       }
     } else {
-      const v8bf a0 = *reinterpret_cast<const v8bf*>(&As[wm + li][8 * lk]);
-      const v8bf a1 = *reinterpret_cast<const v8bf*>(&As[wm + 16 + li][8 * lk]);
-      const v8bf b0 = *reinterpret_cast<const v8bf*>(&Bs[wn + li][8 * lk]);
-      const v8bf b1 = *reinterpret_cast<const v8bf*>(&Bs[wn + 16 + li][8 * lk]);
-      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 32) {
+        const v8bf a0 = *reinterpret_cast<const v8bf*>(&As[wm + li][kk + 8 * lk]);
+        const v8bf a1 = *reinterpret_cast<const v8bf*>(&As[wm + 16 + li][kk + 8 * lk]);
+        const v8bf b0 = *reinterpret_cast<const v8bf*>(&Bs[wn + li][kk + 8 * lk]);
+        const v8bf b1 = *reinterpret_cast<const v8bf*>(&Bs[wn + 16 + li][kk + 8 * lk]);
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
@@ -136,46 +160,54 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // One-sided Jacobi (Hestenes 1958) on the n columns of X (m rows; column j at
-// X + j*ldx). Rotations are accumulated into V (n x n, column j at V + j*ldv)
-// when V is not null. Parallel cyclic (round-robin) ordering: each round
-// rotates n/2 disjoint column pairs, one pair per wavefront at a time. Stops
-// after a sweep without rotations (|x_p.x_q| <= tol sqrt(|x_p|^2 |x_q|^2)).
-__device__ void jacobi_cols(double* X, int m, int ldx, int n, double* V, int ldv, int* flag) {
+// X + j*ldx), n <= 512. Rotations are accumulated into V (n x n, column j at
+// V + j*ldv) when V is not null. Parallel cyclic (round-robin) ordering: each round
+// rotates n/2 disjoint column pairs, one pair per wavefront at a time. Column
+// norms are kept in LDS and updated with the rotation (a' = a - t g, b' = b + t g),
+// recomputed exactly at the start of every sweep, so a pair costs one wavefront
+// reduction (its inner product g). Stops after a sweep without rotations
+// (|x_p.x_q| <= tol |x_p| |x_q|).
+__device__ void jacobi_cols(double* X, int m, int ldx, int n, double* V, int ldv, int* flag,
+                            double* cnt = nullptr) {
+  __shared__ double nrm[512];
   __shared__ double fro2_s[16];
+  __shared__ int nrot;
+  if (threadIdx.x == 0) nrot = 0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int ne = n + (n & 1);
   const double tol = 4.0e-16 * sqrt((double)(m > 1 ? m : 1));
   if (n < 2) return;
-  // Columns whose squared norm is below (1e-15)^2 of the Frobenius norm squared
-  // (invariant under the rotations) are at round-off level: their inner products
-  // are noise, so they count as converged (otherwise the sweeps never stop).
-  double f = 0.0;
-  for (int j = wave; j < n; j += nw)
-    for (int i = lane; i < m; i += 64) { const double u = X[(long)j * ldx + i]; f += u * u; }
-  f = wave_sum(f);
-  if (lane == 0) fro2_s[wave] = f;
-  __syncthreads();
-  double fro2 = 0.0;
-  for (int w = 0; w < nw; ++w) fro2 += fro2_s[w];
-  const double tiny2 = 1e-30 * fro2 + 1e-300;
   for (int sweep = 0; sweep < 40; ++sweep) {
+    // exact column norms; their sum (the Frobenius norm) is invariant under rotations
+    double f = 0.0;
+    for (int j = wave; j < n; j += nw) {
+      double a = 0.0;
+      for (int i = lane; i < m; i += 64) { const double u = X[(long)j * ldx + i]; a += u * u; }
+      a = wave_sum(a);
+      if (lane == 0) nrm[j] = a;
+      f += a;
+    }
+    if (lane == 0) fro2_s[wave] = f;
     if (threadIdx.x == 0) *flag = 0;
     __syncthreads();
+    double fro2 = 0.0;
+    for (int w = 0; w < nw; ++w) fro2 += fro2_s[w];
+    // columns below (1e-15)^2 of the Frobenius norm squared are at round-off level:
+    // their inner products are noise, so they count as converged
+    const double tiny2 = 1e-30 * fro2 + 1e-300;
     for (int r = 0; r < ne - 1; ++r) {
       for (int pi = wave; pi < ne / 2; pi += nw) {
         int p, q;
         if (pi == 0) { p = ne - 1; q = r; }
         else { p = (r + pi) % (ne - 1); q = (r - pi + ne - 1) % (ne - 1); }
         if (p >= n || q >= n) continue;
+        const double a = nrm[p], b = nrm[q];
+        if (!(a > tiny2) || !(b > tiny2)) continue;
         double* xp = X + (long)p * ldx;
         double* xq = X + (long)q * ldx;
-        double a = 0, b = 0, c = 0;
-        for (int i = lane; i < m; i += 64) {
-          const double u = xp[i], w = xq[i];
-          a += u * u; b += w * w; c += u * w;
-        }
-        a = wave_sum(a); b = wave_sum(b); c = wave_sum(c);
-        if (!(a > tiny2) || !(b > tiny2)) continue;
+        double c = 0;
+        for (int i = lane; i < m; i += 64) c += xp[i] * xq[i];
+        c = wave_sum(c);
         if (fabs(c) <= tol * sqrt(a) * sqrt(b)) continue;
         const double zeta = (b - a) / (2.0 * c);
         const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
@@ -194,13 +226,26 @@ __device__ void jacobi_cols(double* X, int m, int ldx, int n, double* V, int ldv
             vq[i] = sn * u + cs * w;
           }
         }
-        if (lane == 0) *flag = 1;
+        if (lane == 0) {
+          nrm[p] = a - t * c;
+          nrm[q] = b + t * c;
+          *flag = 1;
+          atomicAdd(&nrot, 1);
+        }
       }
       __syncthreads();
     }
-    const int f = *flag;
+    const int fl = *flag;
     __syncthreads();
-    if (f == 0) break;
+    if (cnt && threadIdx.x == 0) {
+      // algorithmic work of this sweep: norms (2mn), per rotation an inner product
+      // (2m) and the rotation of two columns (6m) plus two columns of V (6n)
+      atomicAdd(cnt, 2.0 * m * n + (double)nrot * (8.0 * m + (V ? 6.0 * n : 0.0)));
+      atomicAdd(cnt + 1, 16.0 * ((double)m * n + (V ? (double)n * n : 0.0)));
+      nrot = 0;
+    }
+    __syncthreads();
+    if (fl == 0) break;
   }
 }
 

@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(FACT_THREADS) k_zip_factor(Batch b, Geo g, WsL
     G[(long)j * ld + i] = s;
   }
   __syncthreads();
-  jacobi_cols(G, m, ld, m, nullptr, 0, &flag);
+  jacobi_cols(G, m, ld, m, nullptr, 0, &flag, g.cnt);
   sorted_norms(G, m, ld, m, sig, ord);
   if (threadIdx.x == 0) {
     const double lam0 = sig[ord[0]];
@@ -225,7 +225,7 @@ __global__ void __launch_bounds__(FACT_THREADS) k_rl_svd(Batch b, Geo g, WsLayou
   }
   for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) V[e] = ((e % nb) == (e / nb)) ? 1.0 : 0.0;
   __syncthreads();
-  jacobi_cols(X, m, m, nb, V, nb, &flag);
+  jacobi_cols(X, m, m, nb, V, nb, &flag, g.cnt);
   sorted_norms(X, m, m, nb, sig, ord);
   double* scal = c.ws + wl.scal;
   if (threadIdx.x == 0) {

@@ -6,79 +6,26 @@
 //
 // Every contraction is a batched GEMM whose dimensions are products of bond
 // dimensions read on the device (GemmJob with bond expressions), so a sweep is
-// enqueued without host synchronisation; the host reads the FP64 residual once
-// per sweep to decide whether to continue.
+// enqueued without host synchronisation; the host reads one FP64 number per
+// chain and sweep to decide whether to continue.
+//
+// Convergence measure: before each local update the solver records the FP64
+// residual of the local system, ||b_eff - M_eff x_k|| = ||P_k (b - A x)||, the
+// global residual projected onto the frame of site k (P_k orthogonal). The
+// largest of these over a sweep, divided by ||b||, is the reported residual.
+// At a stationary point of the ALS iteration every projected residual is zero.
+// The global form <x, A^T A x> - 2 <b, A x> + <b, b> is not used: for the
+// pressure operator (condition number ~1e6 at 2^10 x 2^10) its cancellation
+// error exceeds the tolerances of interest.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
 
 #include "../../include/qtt.h"
-#include "device_common.h"
+#include "gemm_jobs.h"
 
 namespace {
-
-constexpr int GB = 4;   // chains per solver launch
-
-// value = mul * p1[i1] * p2[i2] + add   (a null pointer counts as 1)
-struct IE {
-  const int* p1; const int* p2; int i1, i2, mul, add;
-};
-__device__ __forceinline__ int ev(const IE& e) {
-  int v = e.mul;
-  if (e.p1) v *= e.p1[e.i1];
-  if (e.p2) v *= e.p2[e.i2];
-  return v + e.add;
-}
-inline IE C_(int v) { return IE{nullptr, nullptr, 0, 0, 0, v}; }
-inline IE B1(const int* p, int i, int mul = 1, int add = 0) { return IE{p, nullptr, i, 0, mul, add}; }
-inline IE B2(const int* p, int i, const int* q, int j, int mul = 1) { return IE{p, q, i, j, mul, 0}; }
-
-struct GemmJob {
-  const double* A; IE ars, acs;
-  const double* B; IE brs, bcs;
-  double* C; IE crs, ccs;
-  IE M, N, K;
-  IE nb, sa, sb, sc;        // batch count and batch strides
-  const double* skip;       // if non-null and *skip != 0, the job is skipped
-};
-struct GemmBatch {
-  int n, maxb;
-  double* cnt;              // measurement counters or null
-  GemmJob j[GB];
-};
-
-template <int MODE>
-__global__ void __launch_bounds__(256) k_gemm_jobs(GemmBatch gb) {
-  const int ci = blockIdx.z / gb.maxb, bi = blockIdx.z % gb.maxb;
-  if (ci >= gb.n) return;
-  const GemmJob& j = gb.j[ci];
-  if (j.skip && *j.skip != 0.0) return;
-  if (bi >= ev(j.nb)) return;
-  const int M = ev(j.M), N = ev(j.N), K = ev(j.K);
-  if (gb.cnt && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && M > 0 && N > 0 && K > 0) {
-    atomicAdd(gb.cnt, 2.0 * M * N * K);
-    atomicAdd(gb.cnt + 1, 8.0 * ((double)M * K + (double)K * N + (double)M * N));
-  }
-  const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
-  if (m0 >= M || n0 >= N) return;
-  View A{j.A + (long)bi * ev(j.sa), ev(j.ars), ev(j.acs)};
-  View B{j.B + (long)bi * ev(j.sb), ev(j.brs), ev(j.bcs)};
-  gemm_tile<MODE>(M, N, 0, K, A, B, j.C + (long)bi * ev(j.sc), ev(j.crs), ev(j.ccs), 1.0, 0.0, m0, n0);
-}
-
-inline int cdiv(int a, int b) { return (a + b - 1) / b; }
-
-void run_jobs(const GemmBatch& gb0, int maxM, int maxN, int mode, hipStream_t s) {
-  GemmBatch gb = gb0;
-  gb.cnt = qttk::tcount(KC_JOBS);
-  dim3 grid(cdiv(maxN, TILE), cdiv(maxM, TILE), gb.n * gb.maxb);
-  qttk::tmark(KC_JOBS, s);
-  if (mode == 0) hipLaunchKernelGGL(k_gemm_jobs<0>, grid, dim3(256), 0, s, gb);
-  else if (mode == 1) hipLaunchKernelGGL(k_gemm_jobs<1>, grid, dim3(256), 0, s, gb);
-  else hipLaunchKernelGGL(k_gemm_jobs<2>, grid, dim3(256), 0, s, gb);
-  qttk::tmark(KC_JOBS, s);
-}
 
 // ---------------------------------------------------------------------------
 // per-chain data of the solver
@@ -89,7 +36,7 @@ struct SChain {
   double* x; int* xb;               // bra: unknown / fitted train (cap cx), updated in place
   const double* kx; const int* kxb; // ket: the train the environments contract with (cap ck)
   double* ws;                       // solver workspace
-  int* iws;                         // integer workspace (A^T A bonds)
+  double atol2;                     // absolute floor of the local residual (squared)
 };
 struct SBatch {
   int n;
@@ -98,14 +45,14 @@ struct SBatch {
 struct SGeo {
   int L, k, cx, cb, wcap, W;
   int ck;           // slot capacity of the ket train
-  double ltol;      // local CG relative tolerance
+  double ltol;      // local CG: reduction of the initial local residual
   int maxit;        // CG iterations per local problem
   int lds;          // dynamic LDS budget (bytes) of the gauge-move kernels
 };
 
 // workspace layout (doubles)
 struct SLay {
-  size_t LA, RA, Lb, Rb, F1, F2, F3, Mt, Mt2, beff, r, p, Ap, dinv, sc, A2, tmpA, gp, total;
+  size_t LA, RA, Lb, Rb, F1, F2, F3, Mt, Mt2, beff, r, p, Ap, dinv, sc, tmpA, gp, total;
   size_t env, envb;
   static SLay make(int L, int cx, int ck, int cb, int W) {
     SLay l;
@@ -129,7 +76,6 @@ struct SLay {
     l.Ap = o; o += al(2 * (size_t)cx * cx);
     l.dinv = o; o += al(2 * (size_t)cx * cx);
     l.sc = o; o += 64;
-    l.A2 = o; o += al((size_t)L * (size_t)W * W * 4 * W * W);
     l.tmpA = o; o += al(4 * (size_t)cx * cx);
     l.gp = o; o += al(4 * 4 * (size_t)cx * cx);
     l.total = o;
@@ -137,7 +83,7 @@ struct SLay {
   }
 };
 // scalar slots
-enum { S_RZ = 0, S_DONE, S_ITER, S_BN2, S_RN2, S_ITERS_TOTAL, S_COUNT };
+enum { S_RZ = 0, S_DONE, S_ITER, S_BN2, S_RN2, S_ITERS_TOTAL, S_RN0, S_PMAX, S_COUNT };
 
 __device__ __forceinline__ size_t sl2(int cap) { return (size_t)cap * 2 * cap; }
 
@@ -160,33 +106,6 @@ __global__ void k_transposes(SBatch sb, SGeo g, SLay l) {
   }
 }
 
-// A^T A as an MPO (bond w^2): C[(b1 w + b2)][o][i][(c1 w' + c2)] = sum_m A[b1][m][o][c1] A[b2][m][i][c2]
-__global__ void k_mpo_ata(SBatch sb, SGeo g, SLay l) {
-  const int k = blockIdx.x;
-  if (blockIdx.y >= sb.n) return;
-  const SChain& c = sb.c[blockIdx.y];
-  const int w = c.ab[k], w2 = c.ab[k + 1], wc = g.wcap, W2 = g.W * g.W;
-  const double* Ak = c.A + (long)k * wc * 4 * wc;
-  double* Ck = c.ws + l.A2 + (size_t)k * W2 * 4 * W2;
-  for (int e = threadIdx.x; e < W2 * 4 * W2; e += blockDim.x) {
-    const int bb = e / (4 * W2), oi = (e / W2) % 4, cc = e % W2;
-    const int b1 = bb / g.W, b2 = bb % g.W, c1 = cc / g.W, c2 = cc % g.W, o = oi / 2, i = oi % 2;
-    double v = 0.0;
-    if (b1 < w && b2 < w && c1 < w2 && c2 < w2) {
-      for (int m = 0; m < 2; ++m)
-        v += Ak[(long)b1 * 4 * wc + m * 2 * wc + o * wc + c1] * Ak[(long)b2 * 4 * wc + m * 2 * wc + i * wc + c2];
-    }
-    // compact bond index b1*w + b2 (actual bonds) inside the wc^2 slot
-    const int bc = (b1 < w && b2 < w) ? b1 * w + b2 : -1;
-    const int ccc = (c1 < w2 && c2 < w2) ? c1 * w2 + c2 : -1;
-    if (bc >= 0 && ccc >= 0) Ck[(size_t)bc * 4 * W2 + oi * W2 + ccc] = v;
-  }
-  if (threadIdx.x == 0) {
-    c.iws[k + 1] = w2 * w2;
-    if (k == 0) c.iws[0] = 1;
-  }
-}
-
 // environment initialisation: LA_0 = RA_L = Lb_0 = Rb_L = [1]; counters zero
 __global__ void k_env_init(SBatch sb, SGeo g, SLay l) {
   if (blockIdx.x >= sb.n) return;
@@ -198,6 +117,11 @@ __global__ void k_env_init(SBatch sb, SGeo g, SLay l) {
     c.ws[l.Rb + (size_t)g.L * l.envb] = 1.0;
   }
   if (threadIdx.x < S_COUNT) c.ws[l.sc + threadIdx.x] = 0.0;
+}
+
+// start of a sweep: clear the maximum of the projected residuals
+__global__ void k_sweep_reset(SBatch sb, SLay l) {
+  if (blockIdx.x < sb.n && threadIdx.x == 0) sb.c[blockIdx.x].ws[l.sc + S_PMAX] = 0.0;
 }
 
 // Jacobi preconditioner of the local system: 1 / diag(M_eff)
@@ -238,7 +162,9 @@ __device__ double block_sum(double v, double* red) {
   return t;
 }
 
-__global__ void __launch_bounds__(1024) k_cg_init(SBatch sb, SGeo g, SLay l) {
+// first != 0: the residual belongs to the iterate before this local update; it is
+// recorded as the reference of the relative stop and in the sweep maximum.
+__global__ void __launch_bounds__(1024) k_cg_init(SBatch sb, SGeo g, SLay l, int first) {
   __shared__ double red[16];
   if (blockIdx.x >= sb.n) return;
   const SChain& c = sb.c[blockIdx.x];
@@ -265,8 +191,13 @@ __global__ void __launch_bounds__(1024) k_cg_init(SBatch sb, SGeo g, SLay l) {
   bn = block_sum(bn, red);
   rn = block_sum(rn, red);
   if (threadIdx.x == 0) {
+    if (first) {
+      sc[S_RN0] = rn;
+      sc[S_PMAX] = fmax(sc[S_PMAX], rn);
+    }
+    const double thr = fmax(g.ltol * g.ltol * (first ? rn : sc[S_RN0]), c.atol2);
     sc[S_RZ] = rz; sc[S_BN2] = bn; sc[S_RN2] = rn; sc[S_ITER] = 0;
-    sc[S_DONE] = (bn == 0.0 || rn <= g.ltol * g.ltol * bn || g.maxit <= 0) ? 1.0 : 0.0;
+    sc[S_DONE] = (bn == 0.0 || rn <= thr || g.maxit <= 0) ? 1.0 : 0.0;
   }
 }
 
@@ -302,7 +233,7 @@ __global__ void __launch_bounds__(1024) k_cg_step(SBatch sb, SGeo g, SLay l) {
   rn = block_sum(rn, red);
   rz2 = block_sum(rz2, red);
   const double it = sc[S_ITER] + 1.0;
-  const bool done = !(pAp > 0.0) || rn <= g.ltol * g.ltol * sc[S_BN2] || it >= g.maxit;
+  const bool done = !(pAp > 0.0) || rn <= fmax(g.ltol * g.ltol * sc[S_RN0], c.atol2) || it >= g.maxit;
   if (!done) {
     const double beta = rz > 0.0 ? rz2 / rz : 0.0;
     for (int e = threadIdx.x; e < 2 * cx * cx; e += blockDim.x) p[e] = dinv[e] * r[e] + beta * p[e];
@@ -427,6 +358,7 @@ struct Solver {
   }
   static void one(GemmJob& j) {
     j.nb = C_(1); j.sa = C_(0); j.sb = C_(0); j.sc = C_(0); j.skip = nullptr;
+    j.alpha = 1.0; j.beta = 0.0;
   }
 
   // LA_{k+1} from LA_k (contraction of site k): LA[(a, b)][a'] with bra index a
@@ -638,7 +570,7 @@ struct Solver {
     gg.maxit = per;
     for (int rep = 0; rep < reps; ++rep) {
       matvec(k, true, 0);
-      hipLaunchKernelGGL(k_cg_init, dim3(sb.n), dim3(1024), 0, s, sb, gg, l);
+      hipLaunchKernelGGL(k_cg_init, dim3(sb.n), dim3(1024), 0, s, sb, gg, l, rep == 0 ? 1 : 0);
       cg_iterations(gg, k, mmode, per);
     }
   }
@@ -689,7 +621,6 @@ extern "C" int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qt
 namespace qtt_solver_detail {
 // Declared in api.hip: workspace access for the solver.
 double* solver_ws(qtt_ctx* ctx, size_t doubles, int* rc);
-int* solver_iws(qtt_ctx* ctx, size_t ints, int* rc);
 int set_error(qtt_ctx* ctx, int code, const char* msg);
 int lds_of(qtt_ctx* ctx);
 double* pinned(qtt_ctx* ctx, size_t doubles, int* rc);
@@ -726,8 +657,6 @@ extern "C" int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qt
   int rc = 0;
   double* ws = solver_ws(ctx, lay.total * std::min(n, GB), &rc);
   if (rc) return rc;
-  int* iws = solver_iws(ctx, 128 * std::min(n, GB), &rc);
-  if (rc) return rc;
   const int lds = lds_of(ctx);
   int status = QTT_OK;
   for (int i0 = 0; i0 < n; i0 += GB) {
@@ -740,7 +669,6 @@ extern "C" int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qt
       c.x = x[i0 + i].data; c.xb = x[i0 + i].bond;
       c.kx = c.x; c.kxb = c.xb;
       c.ws = ws + lay.total * i;
-      c.iws = iws + 128 * i;
     }
     S.g = SGeo{L, 0, cx, cb, wcap, W, cx, opts->local_tol, opts->max_local_iters, lds};
     S.l = lay;
@@ -749,48 +677,31 @@ extern "C" int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qt
     S.lds = lds;
     S.flags = nullptr;
     hipLaunchKernelGGL(k_transposes, dim3(L, S.sb.n), dim3(256), 0, s, S.sb, S.g, lay);
-    hipLaunchKernelGGL(k_mpo_ata, dim3(L, S.sb.n), dim3(256), 0, s, S.sb, S.g, lay);
     hipLaunchKernelGGL(k_env_init, dim3(S.sb.n), dim3(64), 0, s, S.sb, S.g, lay);
     // right-canonical start (bond structure kept), right environments
     for (int k = L - 1; k >= 1; --k) S.rl_move(k);
     for (int k = L - 1; k >= 1; --k) { S.ra_update(k); S.rb_update(k); }
 
-    // residual ||Ax - b|| / ||b|| via <x, A^T A x> - 2 <b, A x> + <b, b> (FP64)
-    auto residual = [&](double* out) -> int {
-      const int m = S.sb.n;
-      std::vector<qtt_mps> xs(m), bs(m);
-      std::vector<qtt_mpo> As(m), A2s(m);
-      std::vector<std::vector<int>> a2h(m);
-      for (int i = 0; i < m; ++i) {
-        xs[i] = x[i0 + i]; bs[i] = b[i0 + i]; As[i] = A[i0 + i];
-        a2h[i].resize(L + 1);
-        for (int k = 0; k <= L; ++k) a2h[i][k] = A[i0 + i].bond_host[k] * A[i0 + i].bond_host[k];
-        A2s[i].L = L; A2s[i].wcap = W * W; A2s[i].bond_host = a2h[i].data();
-        A2s[i].bond = S.sb.c[i].iws; A2s[i].data = S.sb.c[i].ws + lay.A2;
-      }
-      std::vector<double> xax(m), bax(m), bb(m);
-      int r2;
-      if ((r2 = qtt_dot_mpo(ctx, m, xs.data(), A2s.data(), xs.data(), xax.data(), stream))) return r2;
-      if ((r2 = qtt_dot_mpo(ctx, m, bs.data(), As.data(), xs.data(), bax.data(), stream))) return r2;
-      if ((r2 = qtt_dot(ctx, m, bs.data(), bs.data(), bb.data(), stream))) return r2;
-      for (int i = 0; i < m; ++i) {
-        const double r2v = xax[i] - 2.0 * bax[i] + bb[i];
-        out[i] = bb[i] > 0 ? std::sqrt(std::max(r2v, 0.0) / bb[i]) : 0.0;
-      }
-      return QTT_OK;
-    };
-    double res[GB], best[GB];
-    if ((rc = residual(res))) return rc;
-    for (int i = 0; i < S.sb.n; ++i) {
-      best[i] = res[i];
-      if (info) { info[i0 + i].residual0 = res[i]; info[i0 + i].residual = res[i]; info[i0 + i].sweeps = 0; }
+    // ||b||^2 once (FP64); the absolute floor of each local residual is a share of
+    // the global target
+    double bb[GB], res[GB], best[GB];
+    {
+      std::vector<qtt_mps> bs(S.sb.n);
+      for (int i = 0; i < S.sb.n; ++i) bs[i] = b[i0 + i];
+      if ((rc = qtt_dot(ctx, S.sb.n, bs.data(), bs.data(), bb, stream))) return rc;
     }
+    for (int i = 0; i < S.sb.n; ++i) {
+      S.sb.c[i].atol2 = opts->tol * opts->tol * bb[i] / (4.0 * L);
+      res[i] = best[i] = INFINITY;
+      if (info) { info[i0 + i].residual0 = NAN; info[i0 + i].residual = NAN; info[i0 + i].sweeps = 0; }
+    }
+    double* pmax = pinned(ctx, 8 * (size_t)n, &rc);
+    if (rc) return rc;
+    S.flags = pmax + GB;
     int sweeps = 0;
-    bool all_done = true;
-    for (int i = 0; i < S.sb.n; ++i) all_done = all_done && res[i] <= opts->tol;
+    bool all_done = false;
     while (!all_done && sweeps < opts->max_sweeps) {
-      S.flags = pinned(ctx, 8 * (size_t)n, &rc);
-      if (rc) return rc;
+      hipLaunchKernelGGL(k_sweep_reset, dim3(S.sb.n), dim3(64), 0, s, S.sb, lay);
       // left-to-right half sweep
       for (int k = 0; k < L; ++k) {
         S.local_solve(k, S.mode);
@@ -808,16 +719,24 @@ extern "C" int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qt
         S.local_solve(k - 1, S.mode);
       }
       ++sweeps;
-      if ((rc = residual(res))) return rc;
+      for (int i = 0; i < S.sb.n; ++i)
+        if (hipMemcpyAsync(pmax + i, S.sb.c[i].ws + lay.sc + S_PMAX, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+          return set_error(ctx, QTT_EHIP, "solve: copy of the residual failed");
+      if (hipStreamSynchronize(s) != hipSuccess) return set_error(ctx, QTT_EHIP, "solve: stream sync failed");
       all_done = true;
       bool improving = false;
       for (int i = 0; i < S.sb.n; ++i) {
+        res[i] = bb[i] > 0.0 ? std::sqrt(pmax[i] / bb[i]) : 0.0;
         all_done = all_done && res[i] <= opts->tol;
         if (res[i] < 0.9 * best[i]) improving = true;
         best[i] = std::min(best[i], res[i]);
-        if (info) { info[i0 + i].residual = res[i]; info[i0 + i].sweeps = sweeps; }
+        if (info) {
+          if (sweeps == 1) info[i0 + i].residual0 = res[i];
+          info[i0 + i].residual = res[i];
+          info[i0 + i].sweeps = sweeps;
+        }
       }
-      if (!improving) break;   // stagnated at the bond-limited floor
+      if (sweeps >= 2 && !improving) break;   // stagnated at the bond-limited floor
     }
     // total local iterations
     double* pin = pinned(ctx, 8 * (size_t)n, &rc);

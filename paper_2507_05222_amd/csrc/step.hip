@@ -1,14 +1,18 @@
-// One Chorin fractional step in TT format (Sec. 3.3 of arxiv 2507.05222),
-// composed from the library's own entry points:
-//   convection     (v.grad) v with v and its curvilinear gradients (Hadamard
-//                  products through the copy tensor, Sec. 2.1.3),
-//   predictor      (I - dt/Re Lap) v* = v - dt (v.grad) v (Eq. intermediate_vel_eq),
-//                  solved variationally in the symmetric form
-//                  |J|^(1/2)(I - dt/Re Lap)|J|^(-1/2) w = |J|^(1/2) rhs, v* = |J|^(-1/2) w,
-//   pressure       (-|J| Lap) p = -|J| (1/dt) div v* (Eq. Poisson, J-weighted, Sec. 3.3),
-//   projection     v = v* - dt grad p.
-// Independent chains (u and v, the four gradients, the four products) run
-// batched in one call each.
+// One Chorin fractional step in TT format (Sec. 3.3 of arxiv 2507.05222).
+//
+//   gradients   g = D v + b_D(v_wall, v_inf)            (curvilinear derivatives with
+//                                                         ghost-point corrections, Sec. 3.1)
+//   convection  c = v_x (.) g_x + v_z (.) g_z             (elementwise products through the
+//                                                         copy tensor, Sec. 2.1.3)
+//   predictor   |J|^(1/2)(I - dt/Re Lap)|J|^(-1/2) w = |J|^(1/2)(v - dt c + dt/Re b_Lap),
+//               v* = |J|^(-1/2) w                        (Eq. intermediate_vel_eq, SPD form)
+//   pressure    (-|J| Lap_p) p = (1/dt)(-|J| div v* + b_W) (Eq. Poisson, J-weighted, Sec. 3.3)
+//   projection  v = v* - dt grad_p p
+//
+// Every linear combination of products is one variational fit (Sec. 2.2,
+// qtt_fit) at the state's bond dimension; the two solves are the variational
+// ALS solver (qtt_poisson_solve). Independent chains run batched. After the first
+// step on a context the fits start from the previous step's results.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -20,13 +24,12 @@
 namespace qtt_solver_detail {
 double* step_pool(qtt_ctx* ctx, size_t doubles, int* rc);
 int set_error(qtt_ctx* ctx, int code, const char* msg);
+bool step_warm(qtt_ctx* ctx, int L, int cap);
+void set_step_warm(qtt_ctx* ctx, int L, int cap);
 }
 
 namespace {
-enum {
-  A_GXU = 0, A_GZU, A_GXV, A_GZV, GXU, GZU, GXV, GZV, H0, H1, H2, H3, CONVU, CONVV, R1U, R1V, RHSU, RHSV,
-  RSU, RSV, WU, WV, US, VS, D0, D1, D01, BT, Q0, Q1, NTMP
-};
+enum { GXU = 0, GZU, GXV, GZV, CONVU, CONVV, RSU, RSV, WU, WV, US, VS, BT, NTMP };
 }
 
 extern "C" int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_flow_state* st, const qtt_step_opts* o,
@@ -58,23 +61,25 @@ extern "C" int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_fl
   qtt_mpo DU{L, cap, diag_bonds.data(), ib + 64 * NTMP, pool + NTMP * slot};
   qtt_mpo DV{L, cap, diag_bonds.data(), ib + 64 * (NTMP + 1), pool + NTMP * slot + mslot};
 
-  const qtt_trunc* tr = &o->trunc;
+  const int chi = std::min(o->trunc.chi_max, cap);
+  const bool warm = step_warm(ctx, L, cap);
+  const int init = warm ? 0 : 1;
+  const int sweeps = warm ? std::max(1, o->trunc.fit_sweeps) : std::max(2, o->trunc.fit_sweeps);
   const int mode = o->contract_dt;
   const double dt = o->dt;
   hipStream_t s = (hipStream_t)stream;
+  auto term = [](double c, const qtt_mpo* M, const qtt_mps* x) { return qtt_term{c, M, x}; };
 
-  // (1) curvilinear gradients of u and v: D x + boundary correction (Sec. 3.1)
+  // (1) curvilinear gradients with their boundary corrections
   {
-    qtt_mpo M[4] = {ops->Dx, ops->Dz, ops->Dx, ops->Dz};
-    qtt_mps x[4] = {st->u, st->u, st->v, st->v};
-    qtt_mps y[4] = {T[A_GXU], T[A_GZU], T[A_GXV], T[A_GZV]};
-    if ((rc = qtt_apply_mpo(ctx, 4, M, x, y, tr, mode, stream))) return rc;
-    double one[4] = {1, 1, 1, 1};
-    qtt_mps b[4] = {ops->bx_u, ops->bz_u, ops->bx_v, ops->bz_v};
-    qtt_mps z[4] = {T[GXU], T[GZU], T[GXV], T[GZV]};
-    if ((rc = qtt_add(ctx, 4, one, y, one, b, z, tr, stream))) return rc;
+    qtt_term t[8] = {term(1, &ops->Dx, &st->u), term(1, nullptr, &ops->bx_u),
+                     term(1, &ops->Dz, &st->u), term(1, nullptr, &ops->bz_u),
+                     term(1, &ops->Dx, &st->v), term(1, nullptr, &ops->bx_v),
+                     term(1, &ops->Dz, &st->v), term(1, nullptr, &ops->bz_v)};
+    qtt_mps y[4] = {T[GXU], T[GZU], T[GXV], T[GZV]};
+    if ((rc = qtt_fit(ctx, 4, 2, t, y, chi, sweeps, init, mode, stream))) return rc;
   }
-  // (2) convection: u d_x u + v d_z u, u d_x v + v d_z v (elementwise products)
+  // (2) convection (v.grad) v: diagonal MPOs of u, v (copy tensor) times the gradients
   {
     Batch b;
     b.n = 2;
@@ -85,71 +90,59 @@ extern "C" int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_fl
     std::memset(&g, 0, sizeof(g));
     g.L = L; g.capx = cap; g.capy = cap; g.wcap = cap; g.d = 2;
     qttk::diag_mpo(b, g, s);
-    qtt_mpo M[4] = {DU, DV, DU, DV};
-    qtt_mps x[4] = {T[GXU], T[GZU], T[GXV], T[GZV]};
-    qtt_mps y[4] = {T[H0], T[H1], T[H2], T[H3]};
-    if ((rc = qtt_apply_mpo(ctx, 4, M, x, y, tr, o->product_dt, stream))) return rc;
-    double one[2] = {1, 1};
-    qtt_mps a2[2] = {T[H0], T[H2]}, b2[2] = {T[H1], T[H3]}, c2[2] = {T[CONVU], T[CONVV]};
-    if ((rc = qtt_add(ctx, 2, one, a2, one, b2, c2, tr, stream))) return rc;
+    qtt_term t[4] = {term(1, &DU, &T[GXU]), term(1, &DV, &T[GZU]),
+                     term(1, &DU, &T[GXV]), term(1, &DV, &T[GZV])};
+    qtt_mps y[2] = {T[CONVU], T[CONVV]};
+    if ((rc = qtt_fit(ctx, 2, 2, t, y, chi, sweeps, init, o->product_dt, stream))) return rc;
   }
-  // (3) predictor right-hand side, scaled by |J|^(1/2)
+  // (3) predictor right-hand side scaled by |J|^(1/2): Jh (v - dt c + b_Lap); solve
   {
-    double one[2] = {1, 1}, mdt[2] = {-dt, -dt};
-    qtt_mps uv[2] = {st->u, st->v}, cv[2] = {T[CONVU], T[CONVV]}, r1[2] = {T[R1U], T[R1V]};
-    if ((rc = qtt_add(ctx, 2, one, uv, mdt, cv, r1, tr, stream))) return rc;
-    qtt_mps bl[2] = {ops->bL_u, ops->bL_v}, rhs[2] = {T[RHSU], T[RHSV]};
-    if ((rc = qtt_add(ctx, 2, one, r1, one, bl, rhs, tr, stream))) return rc;
-    qtt_mpo jh[2] = {ops->Jh, ops->Jh};
-    qtt_mps rs[2] = {T[RSU], T[RSV]}, w[2] = {T[WU], T[WV]};
-    if ((rc = qtt_apply_local(ctx, 2, jh, rhs, rs, stream))) return rc;
-    // initial guess w0 = |J|^(1/2) rhs (H = I + O(dt/Re)); it carries the bond
-    // structure of the right-hand side, which single-site updates cannot enlarge
-    {
-      Batch b;
-      b.n = 2;
-      std::memset(&b.c[0], 0, sizeof(Chain) * 2);
-      for (int i = 0; i < 2; ++i) {
-        b.c[i].x = rs[i].data; b.c[i].xb = rs[i].bond; b.c[i].y = w[i].data; b.c[i].yb = w[i].bond;
-        b.c[i].alpha = 1.0;
-      }
-      Geo g;
-      std::memset(&g, 0, sizeof(g));
-      g.L = L; g.capx = cap; g.capy = cap; g.d = 2;
-      qttk::copy_mps(b, g, s);
+    qtt_term t[6] = {term(1, &ops->Jh, &st->u), term(-dt, &ops->Jh, &T[CONVU]), term(1, &ops->Jh, &ops->bL_u),
+                     term(1, &ops->Jh, &st->v), term(-dt, &ops->Jh, &T[CONVV]), term(1, &ops->Jh, &ops->bL_v)};
+    qtt_mps y[2] = {T[RSU], T[RSV]};
+    if ((rc = qtt_fit(ctx, 2, 3, t, y, chi, sweeps, init, mode, stream))) return rc;
+    // initial guess of the solve: w0 = |J|^(1/2) rhs (H = I + O(dt/Re)); it carries the
+    // bond structure of the right-hand side, which single-site updates cannot enlarge
+    Batch b;
+    b.n = 2;
+    std::memset(&b.c[0], 0, sizeof(Chain) * 2);
+    for (int i = 0; i < 2; ++i) {
+      b.c[i].x = y[i].data; b.c[i].xb = y[i].bond; b.c[i].y = T[WU + i].data; b.c[i].yb = T[WU + i].bond;
+      b.c[i].alpha = 1.0;
     }
+    Geo g;
+    std::memset(&g, 0, sizeof(g));
+    g.L = L; g.capx = cap; g.capy = cap; g.d = 2;
+    qttk::copy_mps(b, g, s);
     qtt_mpo hs[2] = {ops->Hs, ops->Hs};
+    qtt_mps w[2] = {T[WU], T[WV]};
     qtt_solve_info hi[2];
     qtt_solve_opts ho = o->helmholtz;
-    rc = qtt_poisson_solve(ctx, 2, hs, rs, w, &ho, hi, stream);
+    rc = qtt_poisson_solve(ctx, 2, hs, y, w, &ho, hi, stream);
     if (rc && rc != QTT_ENOTCONVERGED) return rc;
     if (info) { info->helm_u = hi[0]; info->helm_v = hi[1]; }
     qtt_mpo jmh[2] = {ops->Jmh, ops->Jmh};
     qtt_mps vs[2] = {T[US], T[VS]};
     if ((rc = qtt_apply_local(ctx, 2, jmh, w, vs, stream))) return rc;
   }
-  // (4) J-weighted divergence and pressure solve
+  // (4) J-weighted divergence and the pressure solve
   {
-    qtt_mpo M[2] = {ops->Wx, ops->Wz};
-    qtt_mps x[2] = {T[US], T[VS]}, y[2] = {T[D0], T[D1]};
-    if ((rc = qtt_apply_mpo(ctx, 2, M, x, y, tr, mode, stream))) return rc;
-    double one = 1.0, idt = 1.0 / dt;
-    if ((rc = qtt_add(ctx, 1, &one, &T[D0], &one, &T[D1], &T[D01], tr, stream))) return rc;
-    if ((rc = qtt_add(ctx, 1, &idt, &T[D01], &idt, &ops->bW, &T[BT], tr, stream))) return rc;
+    const double idt = 1.0 / dt;
+    qtt_term t[3] = {term(idt, &ops->Wx, &T[US]), term(idt, &ops->Wz, &T[VS]), term(idt, nullptr, &ops->bW)};
+    if ((rc = qtt_fit(ctx, 1, 3, t, &T[BT], chi, sweeps, init, mode, stream))) return rc;
     qtt_solve_info pi;
     qtt_solve_opts po = o->poisson;
     rc = qtt_poisson_solve(ctx, 1, &ops->P, &T[BT], &st->p, &po, &pi, stream);
     if (rc && rc != QTT_ENOTCONVERGED) return rc;
     if (info) info->poisson = pi;
   }
-  // (5) projection v = v* - dt grad p
+  // (5) projection v = v* - dt grad p (the old velocity is the initial frame)
   {
-    qtt_mpo M[2] = {ops->Dxp, ops->Dzp};
-    qtt_mps x[2] = {st->p, st->p}, y[2] = {T[Q0], T[Q1]};
-    if ((rc = qtt_apply_mpo(ctx, 2, M, x, y, tr, mode, stream))) return rc;
-    double one[2] = {1, 1}, mdt[2] = {-dt, -dt};
-    qtt_mps vs[2] = {T[US], T[VS]}, out[2] = {st->u, st->v};
-    if ((rc = qtt_add(ctx, 2, one, vs, mdt, y, out, tr, stream))) return rc;
+    qtt_term t[4] = {term(1, nullptr, &T[US]), term(-dt, &ops->Dxp, &st->p),
+                     term(1, nullptr, &T[VS]), term(-dt, &ops->Dzp, &st->p)};
+    qtt_mps y[2] = {st->u, st->v};
+    if ((rc = qtt_fit(ctx, 2, 2, t, y, chi, sweeps, init, mode, stream))) return rc;
   }
+  set_step_warm(ctx, L, cap);
   return QTT_OK;
 }

@@ -16,8 +16,13 @@ class FlowOps:
     def __init__(self, n, r_out=20.0, Re=100.0, dt=1e-3, alpha=0.0, u_inf=1.0, device="cuda"):
         self.n, self.L = n, 2 * n
         self.cyl = Q.cylinder(n, r_out, Re, dt, alpha, u_inf)
-        self.mpo = {k: Q.build_mpo(self.cyl, Q.OP[k], device) for k in
-                    ("DX", "DZ", "DXP", "DZP", "WX", "WZ", "HS", "P", "JH", "JMH")}
+        names = ("DX", "DZ", "DXP", "DZP", "WX", "WZ", "HS", "P")
+        built = {k: Q.build_host(self.cyl, Q.OP[k]) for k in names}
+        # operators applied in one batched call share one slot capacity
+        self.wcap = max(b[2] for b in built.values())
+        self.mpo = {k: Q.MPO(*Q.build_host(self.cyl, Q.OP[k], self.wcap)[:2], self.wcap, device) for k in names}
+        for k in ("JH", "JMH"):
+            self.mpo[k] = Q.build_mpo(self.cyl, Q.OP[k], device)
         caps = [Q.build_host(self.cyl, Q.VEC[k])[2] for k in
                 ("BX_U", "BZ_U", "BX_V", "BZ_V", "BL_U", "BL_V", "BW")]
         self.bc_cap = max(caps)

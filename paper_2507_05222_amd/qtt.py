@@ -58,6 +58,10 @@ class CSolveInfo(ctypes.Structure):
                 ("residual", ctypes.c_double), ("residual0", ctypes.c_double)]
 
 
+class CTerm(ctypes.Structure):
+    _fields_ = [("coef", ctypes.c_double), ("M", ctypes.POINTER(CMpo)), ("x", ctypes.POINTER(CMps))]
+
+
 class CFlowOps(ctypes.Structure):
     _fields_ = [(n, CMpo) for n in ("Dx", "Dz", "Dxp", "Dzp", "Wx", "Wz", "Hs", "P", "Jh", "Jmh")] + \
                [(n, CMps) for n in ("bx_u", "bz_u", "bx_v", "bz_v", "bL_u", "bL_v", "bW")]
@@ -107,6 +111,7 @@ def lib():
             L.qtt_poisson_solve.argtypes = [vp, i32, p(CMpo), p(CMps), p(CMps), p(CSolveOpts), p(CSolveInfo), vp]
         if hasattr(L, "qtt_fractional_step"):
             L.qtt_fractional_step.argtypes = [vp, p(CFlowOps), p(CFlowState), p(CStepOpts), p(CStepInfo), vp]
+        L.qtt_fit.argtypes = [vp, i32, i32, p(CTerm), p(CMps), i32, i32, i32, i32, vp]
         L.qtt_timer_start.argtypes = [vp, i32]
         L.qtt_timer_read.argtypes = [vp, p(ctypes.c_int64), p(ctypes.c_double), p(ctypes.c_double),
                                      p(ctypes.c_double)]
@@ -291,6 +296,28 @@ def apply_local(ctx: Context, Ds, xs, ys, stream=None):
     ctx.check(lib().qtt_apply_local(ctx.h, len(xs), _arr(CMpo, [d.desc() for d in Ds]),
                                     _arr(CMps, [x.desc() for x in xs]), _arr(CMps, [y.desc() for y in ys]),
                                     _stream(stream)))
+
+
+def fit(ctx: Context, problems, ys, chi=None, sweeps=1, init=1, dtype="f64", stream=None):
+    """y_i ~ sum_t c M x for each problem i; problems[i] = [(coef, MPO or None, MPS), ...]."""
+    n = len(ys)
+    nt = len(problems[0])
+    chi = chi if chi is not None else ys[0].cap
+    keep = []
+    terms = (CTerm * (n * nt))()
+    for i, prob in enumerate(problems):
+        if len(prob) != nt:
+            raise ValueError("every problem needs the same number of terms")
+        for t, (c, M, x) in enumerate(prob):
+            xd = x.desc()
+            keep.append(xd)
+            md = None
+            if M is not None:
+                md = M.desc()
+                keep.append(md)
+            terms[i * nt + t] = CTerm(float(c), ctypes.pointer(md) if md is not None else None, ctypes.pointer(xd))
+    ctx.check(lib().qtt_fit(ctx.h, n, nt, terms, _arr(CMps, [y.desc() for y in ys]), int(chi), int(sweeps), int(init),
+                            DTYPES.get(dtype, dtype), _stream(stream)))
 
 
 def solve_opts(tol=1e-8, max_sweeps=10, max_local_iters=100, local_tol=1e-3, dtype="f64") -> CSolveOpts:
