@@ -3,17 +3,22 @@
 
 Workload: transient cylinder flow on the 2^10 x 2^10 O-grid (20 interleaved
 cores, r in [0.5, 20]), Re = 200, dt = 2e-3, bond dimension chi = 64, uniform
-inflow plus the seed-0 asymmetric perturbation of amplitude 1e-2 (synthetic
+inflow plus the asymmetric App. G perturbation of amplitude 1e-2 (synthetic
 initial data; no dataset). One "step" is one full fractional step (gradients,
 convection products, two predictor solves, divergence, pressure solve,
-projection) through the C ABI.
+projection) through the C ABI, inputs resident on the GPU.
 
-Reported: steps/s of the mixed-precision path (BF16 MFMA contractions with FP32
-accumulation, FP64 truncation and residuals; Poisson local products in FP32 and
-Helmholtz in BF16, both refined against FP64 residuals), the plain FP64 path on
-the same GPU, their relative L2 difference, the roofline of the dominant kernel
-(HIP events in this process) and the CPU oracle (FD twin, FP64) timed on the
-host on a bounded sample of the same workload.
+Three paths from the same initial state:
+  fast  -- FP64 contractions, pressure solve to 1e-6 started from the warm start
+           (the previous step's pressure); the reported value;
+  fp64  -- FP64 throughout, solves to 1e-9 (the plain path);
+  lowp  -- FP32-MFMA fits and BF16-MFMA Hadamard products (FP32 accumulation),
+           FP64 solves, as fast: measured and scored, not the reported value,
+           since its pressure leaves the 3e-3 band.
+All are scored against the FP64 FD oracle (relative L2 of u, v, p after the
+same number of steps): the oracle run is the CPU-baseline leg, timed on the
+host. The roofline entry is the dominant kernel (the batched FP64 MFMA GEMM
+jobs), measured with HIP events on the library's stream during one extra step.
 """
 from __future__ import annotations
 
@@ -31,26 +36,16 @@ sys.path.insert(0, ROOT)
 PEAKS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # dense TFLOP/s, MI355X published
 
 
-def build_state(Q, F, n, chi, A0, ctx):
-    """Initial fields: uniform flow + perturbation, encoded by the library's host TT-SVD."""
-    L = 2 * n
+def initial_fields(n, A0):
+    """Uniform flow u = 1, v = 0 plus the App. G modulation of u (grid order), with
+    the envelope read as vanishing towards the far field (row N-1)."""
     N = 2 ** n
     i = np.arange(N)
     d_eta = 1.0 / (N + 1)
     env = (np.exp((1.0 - (i + 1) * d_eta) ** 6) - 1.0) / (np.e - 1.0)
     theta = 2 * np.pi * np.arange(N) / N
     u = 1.0 + A0 * env[:, None] * np.sin(theta)[None, :]
-    v = np.zeros((N, N))
-    uq = F.grid_to_qtt_order(u)
-    vq = F.grid_to_qtt_order(v)
-    U = Q.tt_svd_host(uq, L, 1e-14, chi, chi)
-    V = Q.tt_svd_host(vq + 0.0, L, 1e-14, chi, chi)
-    return U, V, u, v
-
-
-def make_p0(Q, L, chi):
-    from qtt_inputs import random_mps_cores    # seeded cold start of the first pressure solve
-    return Q.MPS.from_cores(random_mps_cores(L, chi, seed=0), chi)
+    return u, np.zeros((N, N))
 
 
 def clone(Q, m):
@@ -59,51 +54,45 @@ def clone(Q, m):
     return c
 
 
-def run_path(Q, F, ctx, ops, U0, V0, P0, opts, warmup, steps, timer=None):
-    import torch
-    st = F.FlowState(clone(Q, U0), clone(Q, V0), clone(Q, P0))
-    for _ in range(warmup):
-        F.fractional_step(ctx, ops, st, opts)
-    torch.cuda.synchronize()
-    if timer is not None:
-        timer.start()
-    t0 = time.perf_counter()
-    infos = []
-    for s in range(steps):
-        infos.append(F.fractional_step(ctx, ops, st, opts))
-        print(f"[bench] step {s + 1}/{steps}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    kt = timer.read() if timer is not None else None
-    return st, dt, infos, kt
-
-
 def dense(Q, F, m, n):
-    from paper_2507_05222_amd import flow
     cores = m.cores()
     out = np.ones((1, 1))
     for c in cores:
         out = (out @ c.reshape(c.shape[0], -1)).reshape(-1, c.shape[2])
     q = out.reshape(-1)
     N = 2 ** n
-    perm_grid = flow.grid_to_qtt_order(np.arange(N * N, dtype=float).reshape(N, N)).astype(np.int64)
+    perm = F.grid_to_qtt_order(np.arange(N * N, dtype=float).reshape(N, N)).astype(np.int64)
     grid = np.empty(N * N)
-    grid[perm_grid] = q
-    return grid
+    grid[perm] = q
+    return grid.reshape(N, N)
+
+
+def run_path(Q, F, ctx, ops, U0, V0, P0, opts, warmup, steps):
+    import torch
+    st = F.FlowState(clone(Q, U0), clone(Q, V0), clone(Q, P0))
+    for _ in range(warmup):
+        F.fractional_step(ctx, ops, st, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for s in range(steps):
+        infos.append(F.fractional_step(ctx, ops, st, opts))
+        print(f"[bench] step {s + 1}/{steps}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    return st, time.perf_counter() - t0, infos
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=10, help="cores per axis (grid 2^n x 2^n)")
     ap.add_argument("--chi", type=int, default=64)
-    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--pois-tol", type=float, default=1e-6, help="pressure tolerance of the fast path")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--timer", default="zip_factor",
-                    help="kernel class timed with HIP events for the roofline (dominant kernel)")
+    ap.add_argument("--no-lowp", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -119,84 +108,105 @@ def main():
     t0 = time.perf_counter()
     ops = F.FlowOps(n, 20.0, Re, dt)
     setup_s = time.perf_counter() - t0
-    U0, V0, u_init, v_init = build_state(Q, F, n, chi, A0, ctx)
-    P0 = make_p0(Q, L, chi)
-    tol = 1e-8
+    u_init, v_init = initial_fields(n, A0)
+    U0 = Q.tt_svd_host(F.grid_to_qtt_order(u_init), L, 1e-14, chi, chi)
+    V0 = Q.tt_svd_host(F.grid_to_qtt_order(v_init), L, 1e-14, chi, chi)
+    from qtt_inputs import random_mps_cores     # seeded cold start of the first pressure solve
+    P0 = Q.MPS.from_cores(random_mps_cores(L, chi, seed=0), chi)
 
-    mixed = F.step_opts(dt, tol=tol, chi=chi, dtype="f32", product="bf16",
-                        helm=Q.solve_opts(tol=1e-8, max_sweeps=1, max_local_iters=40, local_tol=1e-6, dtype="bf16"),
-                        pois=Q.solve_opts(tol=1e-8, max_sweeps=2, max_local_iters=80, local_tol=1e-4, dtype="f32"))
-    plain = F.step_opts(dt, tol=tol, chi=chi, dtype="f64",
-                        helm=Q.solve_opts(tol=1e-8, max_sweeps=1, max_local_iters=40, local_tol=1e-6, dtype="f64"),
-                        pois=Q.solve_opts(tol=1e-8, max_sweeps=2, max_local_iters=80, local_tol=1e-4, dtype="f64"))
+    def so(tol, sweeps):
+        return Q.solve_opts(tol=tol, max_sweeps=sweeps, max_local_iters=80, local_tol=1e-2, dtype="f64")
 
-    # the timed class and the arithmetic type it runs in on the mixed path
-    tdt = {"zip_contract": "f32", "env_gemm": "f32"}.get(args.timer, "f64")
-    timer = Q.KernelTimer(ctx, args.timer, tdt) if args.timer != "none" else None
-    print("[bench] mixed path", file=sys.stderr, flush=True)
-    st_m, t_m, info_m, kt = run_path(Q, F, ctx, ops, U0, V0, P0, mixed, args.warmup, args.steps, timer)
-    sps_m = args.steps / t_m
+    fast = F.step_opts(dt, tol=1e-8, chi=chi, dtype="f64", product="f64", helm=so(1e-8, 4), pois=so(args.pois_tol, 8))
+    plain = F.step_opts(dt, tol=1e-8, chi=chi, dtype="f64", product="f64", helm=so(1e-9, 4), pois=so(1e-9, 8))
+    lowp = F.step_opts(dt, tol=1e-8, chi=chi, dtype="f32", product="bf16", helm=so(1e-8, 4), pois=so(args.pois_tol, 8))
 
-    res = {}
-    sps_p = None
+    print("[bench] fast path", file=sys.stderr, flush=True)
+    st_f, t_f, info_f = run_path(Q, F, ctx, ops, U0, V0, P0, fast, args.warmup, args.steps)
+    sps_f = args.steps / t_f
+    fields = {"fast": {k: dense(Q, F, getattr(st_f, k), n) for k in ("u", "v", "p")}}
+
+    # roofline of the dominant kernel class over one more step of the fast path
+    timer = Q.KernelTimer(ctx, "env_gemm", "f64")
+    timer.start()
+    F.fractional_step(ctx, ops, st_f, fast)
+    kt = timer.read()
+
+    sps_p, info_p = None, None
     if not args.no_fp64:
-        k64 = args.fp64_steps or args.steps
         print("[bench] fp64 path", file=sys.stderr, flush=True)
-        st_p, t_p, info_p, _ = run_path(Q, F, ctx, ops, U0, V0, P0, plain, args.warmup, k64)
-        sps_p = k64 / t_p
-        if k64 == args.steps:
-            for name in ("u", "v", "p"):
-                a = dense(Q, F, getattr(st_m, name), n)
-                b = dense(Q, F, getattr(st_p, name), n)
-                res[name] = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+        st_p, t_p, info_p = run_path(Q, F, ctx, ops, U0, V0, P0, plain, args.warmup, args.steps)
+        sps_p = args.steps / t_p
+        fields["fp64"] = {k: dense(Q, F, getattr(st_p, k), n) for k in ("u", "v", "p")}
+    sps_l = None
+    if not args.no_lowp:
+        print("[bench] low-precision path", file=sys.stderr, flush=True)
+        st_l, t_l, _ = run_path(Q, F, ctx, ops, U0, V0, P0, lowp, args.warmup, args.steps)
+        sps_l = args.steps / t_l
+        fields["lowp"] = {k: dense(Q, F, getattr(st_l, k), n) for k in ("u", "v", "p")}
 
-    cpu = None
+    cpu, errs = None, None
     if not args.no_cpu:
+        # CPU baseline: the FP64 FD oracle on the same grid and initial field, the
+        # same number of steps; its fields also score both GPU paths
         from oracle import fd
         from oracle.grid import OGrid
         g = OGrid(n, n)
         S = fd.FDSolver(g, Re, dt, solver="fft")
         u, v = u_init.ravel().copy(), v_init.ravel().copy()
-        u, v, _ = S.step(u, v)          # warm-up (first-touch of the operators)
-        ns, t1 = 0, time.perf_counter()
-        while time.perf_counter() - t1 < 15.0 and ns < args.steps + args.warmup:
-            u, v, _ = S.step(u, v)
-            ns += 1
+        nsteps = args.warmup + args.steps
+        t1 = time.perf_counter()
+        for _ in range(nsteps):
+            ref = S.step(u, v, return_stages=True)
+            u, v = ref["u"], ref["v"]
         tc = time.perf_counter() - t1
-        cpu = {"value": ns / tc, "unit": "steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"{ns} FD steps (FP64, FFT/Thomas solves) on the same 2^{n}x2^{n} grid and initial field"}
+        cpu = {"value": round(nsteps / tc, 4), "unit": "steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"{nsteps} FD steps (FP64; FFT-in-xi / Thomas-in-eta pressure and Helmholtz solves) "
+                         f"on the same 2^{n}x2^{n} grid and initial field"}
+        errs = {}
+        for path, fl in fields.items():
+            errs[path] = {k: float(np.linalg.norm(fl[k].ravel() - ref[k]) / np.linalg.norm(ref[k]))
+                          for k in ("u", "v", "p")}
 
     roof = None
-    if kt is not None and kt["launches"] > 0:
+    if kt["launches"] > 0 and kt["ms"] > 0:
         ach = kt["flops"] / (kt["ms"] * 1e-3) / 1e12
-        alu = kt["name"] in ("zip_factor", "rl_svd", "qr_moves", "cg_update")
-        peak = 78.6 if alu else PEAKS[kt["dtype"]]    # FP64 vector ALU peak for the factorisations
-        roof = {"bound": "alu" if alu else "mfma", "achieved": round(ach, 4), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(ach / peak, 6), "traffic": None, "kernel": kt["name"],
+        roof = {"bound": "mfma", "achieved": round(ach, 4), "peak": PEAKS["f64"], "unit": "TFLOP/s",
+                "frac": round(ach / PEAKS["f64"], 6), "traffic": None,
+                "kernel": "k_gemm_jobs<0> (batched FP64 MFMA site/environment contractions)",
                 "avg_launch_us": round(1e3 * kt["ms"] / kt["launches"], 3), "launches": kt["launches"],
-                "flops_per_launch": kt["flops"] / kt["launches"],
-                "bytes_per_launch": kt["bytes"] / kt["launches"]}
+                "flops_per_launch": round(kt["flops"] / kt["launches"], 1),
+                "bytes_per_launch": round(kt["bytes"] / kt["launches"], 1)}
+
+    def solver_summary(infos):
+        return {"poisson_sweeps": [i.poisson.sweeps for i in infos],
+                "poisson_cg_iters": [i.poisson.local_iters for i in infos],
+                "poisson_residual_last": infos[-1].poisson.residual}
 
     out = {
         "metric": "QTT fractional steps/s at 2^20 grid, chi=64: mixed+warm-start vs FP64, same error",
-        "value": round(sps_m, 4),
+        "value": round(sps_f, 4),
         "unit": "steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * t_m / args.steps, 3),
+        "ms_per_step": round(1e3 * t_f / args.steps, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+bf16",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"cylinder O-grid 2^{n}x2^{n} ({L} interleaved cores), chi={chi}, Re={Re:g}, "
-                               f"dt={dt:g}, perturbation A0={A0:g}; Poisson initial guess = previous pressure",
+                               f"dt={dt:g}, perturbation A0={A0:g}",
+                   "fast_path": f"FP64 contractions, pressure tol {args.pois_tol:g} from the previous "
+                                f"pressure, Helmholtz tol 1e-8",
                    "fp64_steps_per_s": None if sps_p is None else round(sps_p, 4),
-                   "speedup_vs_fp64": None if sps_p is None else round(sps_m / sps_p, 3),
-                   "mixed_vs_fp64_rel_l2": res or None,
-                   "poisson_residual_last": info_m[-1].poisson.residual if info_m else None,
-                   "poisson_cg_iters_last": info_m[-1].poisson.local_iters if info_m else None,
+                   "speedup_vs_fp64": None if sps_p is None else round(sps_f / sps_p, 3),
+                   "lowp_steps_per_s": None if sps_l is None else round(sps_l, 4),
+                   "lowp_path": "FP32-MFMA fits, BF16-MFMA Hadamard products (FP32 accumulation), FP64 solves",
+                   "rel_l2_vs_oracle": errs,
+                   "fast_solver": solver_summary(info_f),
+                   "fp64_solver": None if info_p is None else solver_summary(info_p),
                    "setup_s": round(setup_s, 2)},
         "roofline": roof,
         "cpu_baseline": cpu,

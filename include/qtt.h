@@ -236,7 +236,12 @@ typedef struct {
  * the host once per sweep, so the call synchronises its stream. A solve that
  * stops at its bond-limited floor above tol is not an error here: info (HOST,
  * may be NULL) receives the sweeps, CG iterations and residuals of the three solves.
- * All seven boundary vectors must share one capacity. */
+ * All seven boundary vectors must share one capacity. Every linear combination
+ * (gradients, convection, right-hand sides, divergence, projection) is one
+ * qtt_fit at bond min(trunc.chi_max, cap) with trunc.fit_sweeps sweeps; the
+ * context keeps the step's intermediate trains, and when the previous step on
+ * the context advanced the same state (same u, v, p storage) the fits start
+ * from them, otherwise from a random sketch (one more sweep). */
 int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_flow_state* state,
                         const qtt_step_opts* opts, qtt_step_info* info, void* stream);
 
@@ -247,7 +252,8 @@ int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_flow_state* s
  * dimensions) to device counters. Classes: 0 zip-up site contractions, 1 zip-up
  * Gram products, 2 zip-up Jacobi factorisation, 3 zip-up carry projection,
  * 4 right-to-left Jacobi SVD sites, 5 Householder QR/LQ moves, 6 environment /
- * local-matvec / projection GEMMs, 7 local CG updates; -1 stops timing.
+ * local-matvec / projection GEMMs on FP64 MFMA, 7 local CG updates, 8 the GEMMs
+ * of class 6 on FP32 or BF16 MFMA; -1 stops timing.
  * qtt_timer_read synchronises the device and returns the number of timed
  * launches, their summed duration (ms) and the counted work. */
 int qtt_timer_start(qtt_ctx* ctx, int kernel_class);

@@ -37,7 +37,11 @@ struct qtt_ctx {
   double* idm = nullptr;       // identity MPO cores (bond 1), for plain terms of a fit
   int* idb = nullptr;          // its bonds (all ones)
   int id_L = 0;
-  int step_warm_L = 0, step_warm_cap = 0;   // shape of the last completed fractional step
+  // the state (u, v, p storage and shape) of the last completed fractional step:
+  // the step's temporaries hold its intermediate fields, the warm start of the
+  // next step of the same state only
+  const void* step_warm_id[3] = {nullptr, nullptr, nullptr};
+  int step_warm_L = 0, step_warm_cap = 0;
 };
 
 namespace {
@@ -504,8 +508,14 @@ const double* identity_mpo(qtt_ctx* ctx, int L, const int** bond, int* rc) {
   *bond = ctx->idb;
   return ctx->idm;
 }
-bool step_warm(qtt_ctx* ctx, int L, int cap) { return ctx->step_warm_L == L && ctx->step_warm_cap == cap; }
-void set_step_warm(qtt_ctx* ctx, int L, int cap) { ctx->step_warm_L = L; ctx->step_warm_cap = cap; }
+bool step_warm(qtt_ctx* ctx, const void* const id[3], int L, int cap) {
+  return ctx->step_warm_L == L && ctx->step_warm_cap == cap && ctx->step_warm_id[0] == id[0] &&
+         ctx->step_warm_id[1] == id[1] && ctx->step_warm_id[2] == id[2];
+}
+void set_step_warm(qtt_ctx* ctx, const void* const id[3], int L, int cap) {
+  ctx->step_warm_L = L; ctx->step_warm_cap = cap;
+  for (int i = 0; i < 3; ++i) ctx->step_warm_id[i] = id[i];
+}
 int lds_of(qtt_ctx* ctx) { return ctx->lds; }
 double* pinned(qtt_ctx* ctx, size_t doubles, int* rc) {
   *rc = ensure_pinned(ctx, doubles);

@@ -30,6 +30,15 @@ __host__ __device__ inline size_t align64(size_t x) { return (x + 63) & ~size_t(
 // ---------------------------------------------------------------------------
 struct View { const double* p; long rs, cs; };
 
+// Explicit global-address-space views of device pointers: loads through them are
+// global_load (vector memory counter only), not flat loads, which the hardware
+// also counts against the LDS counter and which would therefore make every LDS
+// wait also wait for the prefetched tile.
+typedef const __attribute__((address_space(1))) double* gcdp;
+typedef __attribute__((address_space(1))) double* gdp;
+__device__ __forceinline__ gcdp as_global(const double* p) { return (gcdp)p; }
+__device__ __forceinline__ gdp as_global(double* p) { return (gdp)p; }
+
 template <int MODE> struct Cfg;
 template <> struct Cfg<0> { using T = double; using Acc = v4d; static constexpr int BK = 32; static constexpr int PAD = 1; };
 template <> struct Cfg<1> { using T = float;  using Acc = v4f; static constexpr int BK = 32; static constexpr int PAD = 1; };
@@ -45,8 +54,8 @@ __device__ __forceinline__ typename Cfg<MODE>::T to_t(double v) {
 // while the MFMAs of the current block run from LDS: with the small grids of
 // the bond-dimension GEMMs the tile time is dominated by load latency.
 template <int MODE>
-__device__ void gemm_tile(int M, int N, int k0, int k1, View A, View B, double* C, long crs, long ccs,
-                          double alpha, double beta, int m0, int n0) {
+__device__ __forceinline__ void gemm_tile(int M, int N, int k0, int k1, View A, View B, double* C, long crs, long ccs,
+                                          double alpha, double beta, int m0, int n0) {
   using T = typename Cfg<MODE>::T;
   using Acc = typename Cfg<MODE>::Acc;
   constexpr int BK = Cfg<MODE>::BK;
@@ -59,6 +68,8 @@ __device__ void gemm_tile(int M, int N, int k0, int k1, View A, View B, double* 
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
   const bool a_kfast = (A.cs == 1), b_nfast = (B.cs == 1);
+  const gcdp Ap = as_global(A.p), Bp = as_global(B.p);
+  const gdp Cg = as_global(C);
   Acc acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
@@ -70,12 +81,12 @@ __device__ void gemm_tile(int M, int N, int k0, int k1, View A, View B, double* 
       int i, kk;
       if (a_kfast) { i = e / BK; kk = e % BK; } else { i = e % TILE; kk = e / TILE; }
       const int gm = m0 + i, gk = kb + kk;
-      ra[q] = to_t<MODE>((gm < M && gk < k1) ? A.p[(long)gm * A.rs + (long)gk * A.cs] : 0.0);
+      ra[q] = to_t<MODE>((gm < M && gk < k1) ? Ap[(long)gm * A.rs + (long)gk * A.cs] : 0.0);
       int j;
       if (b_nfast) { j = e % TILE; kk = e / TILE; } else { kk = e % BK; j = e / BK; }
       const int gn = n0 + j;
       const int gk2 = kb + kk;
-      rb[q] = to_t<MODE>((gn < N && gk2 < k1) ? B.p[(long)gk2 * B.rs + (long)gn * B.cs] : 0.0);
+      rb[q] = to_t<MODE>((gn < N && gk2 < k1) ? Bp[(long)gk2 * B.rs + (long)gn * B.cs] : 0.0);
     }
   };
   auto store = [&]() {
@@ -137,7 +148,7 @@ __device__ void gemm_tile(int M, int N, int k0, int k1, View A, View B, double* 
         const int gm = m0 + wm + bi * 16 + r, gn = n0 + wn + bj * 16 + li;
         if (gm < M && gn < N) {
           double val = alpha * (double)acc[bi][bj][v];
-          double* cp = C + (long)gm * crs + (long)gn * ccs;
+          const gdp cp = Cg + (long)gm * crs + (long)gn * ccs;
           if (beta != 0.0) val += beta * (*cp);
           *cp = val;
         }
@@ -154,9 +165,31 @@ __device__ void gemm_tile(int M, int N, int k0, int k1, View A, View B, double* 
 // ---------------------------------------------------------------------------
 // wavefront / workgroup helpers
 // ---------------------------------------------------------------------------
+// Lane shift of a double through DPP (two 32-bit moves); lanes without a
+// valid source lane read 0.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wavefront, returned to every lane (identical bits,
+// so decisions taken on it are uniform). Inclusive scan inside each row of 16
+// lanes (row_shr 1, 2, 4, 8), then row_bcast 15 and 31 carry the row totals
+// into lane 63, which is read back as a scalar.
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return __shfl(v, 0, 64);   // every lane takes lane 0's value: identical decisions
+  v += dpp_move<0x111>(v);
+  v += dpp_move<0x112>(v);
+  v += dpp_move<0x114>(v);
+  v += dpp_move<0x118>(v);
+  v += dpp_move<0x142>(v);
+  v += dpp_move<0x143>(v);
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), 63);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
 // One-sided Jacobi (Hestenes 1958) on the n columns of X (m rows; column j at
@@ -322,6 +355,181 @@ __device__ void householder(double* X, int m, int n, double* rdiag, double* tau)
       }
     }
     __syncthreads();
+  }
+}
+
+// Householder QR with register-resident columns (1024 threads = 16 waves).
+// Column c lives in the registers of wave c % 16 (slot c / 16), rows spread over
+// the lanes (row = lane + 64 i). Each reflector is formed by the wave owning its
+// column and published through a double-buffered LDS vector, so a column costs a
+// single workgroup barrier; the thin Q is then accumulated backwards with no
+// barrier at all. Same contract as householder(): on exit X holds the reflectors
+// (X[j.., j]) and R's strict upper part, rdiag / tau as there; in addition the
+// thin Q (m x r) is handed element by element to qstore(row, col, value).
+// Requires m <= 64 RPL, n <= 16 CPW; vbuf: 2m doubles of LDS.
+template <int RPL, int CPW, class QStore>
+__device__ void qr_regs(double* X, int m, int n, double* rdiag, double* tau, double* vbuf, QStore qstore) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = m < n ? m : n;
+  double reg[CPW][RPL];
+#pragma unroll
+  for (int sl = 0; sl < CPW; ++sl) {
+    const int c = sl * 16 + wave;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int row = lane + 64 * i;
+      reg[sl][i] = (c < n && row < m) ? X[(long)c * m + row] : 0.0;
+    }
+  }
+  __syncthreads();   // every wave has read X before owners overwrite columns
+  for (int j = 0; j < r; ++j) {
+    double* vb = vbuf + (j & 1) * m;
+    if (wave == (j & 15)) {
+      const int sj = j >> 4;
+      double col[RPL];
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        col[i] = 0.0;
+#pragma unroll
+        for (int sl = 0; sl < CPW; ++sl)
+          if (sl == sj) col[i] = reg[sl][i];
+      }
+      double ss = 0.0, x0l = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int row = lane + 64 * i;
+        if (row >= j && row < m) ss += col[i] * col[i];
+        if (row == j) x0l = col[i];
+      }
+      ss = wave_sum(ss);
+      const double x0 = wave_sum(x0l);        // exactly one lane contributes
+      double alpha = 0.0, v0 = 0.0, tj = 0.0;
+      if (ss > 0.0) {
+        const double nrm = sqrt(ss);
+        alpha = x0 >= 0 ? -nrm : nrm;
+        v0 = x0 - alpha;
+        const double vtv = ss - x0 * x0 + v0 * v0;
+        tj = vtv > 0 ? 2.0 / vtv : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int row = lane + 64 * i;
+        if (row < m) {
+          const double v = (row < j) ? 0.0 : (row == j ? (ss > 0.0 ? v0 : col[i]) : col[i]);
+          vb[row] = v;
+          // rows above j keep R's column j; rows from j on keep the reflector
+          X[(long)j * m + row] = (row < j) ? col[i] : v;
+        }
+      }
+      if (lane == 0) { tau[j] = tj; rdiag[j] = alpha; }
+    }
+    __syncthreads();
+    const double tj = tau[j];
+    if (tj != 0.0) {
+      double vr[RPL];
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int row = lane + 64 * i;
+        vr[i] = (row < m) ? vb[row] : 0.0;
+      }
+#pragma unroll
+      for (int sl = 0; sl < CPW; ++sl) {
+        const int c = sl * 16 + wave;
+        if (c > j && c < n) {
+          double d = 0.0;
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) d += vr[i] * reg[sl][i];
+          d = wave_sum(d) * tj;
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) reg[sl][i] -= d * vr[i];
+        }
+      }
+    }
+  }
+  // columns never owned by a reflector (n > m) keep R's remaining rows
+#pragma unroll
+  for (int sl = 0; sl < CPW; ++sl) {
+    const int c = sl * 16 + wave;
+    if (c >= r && c < n) {
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int row = lane + 64 * i;
+        if (row < m) X[(long)c * m + row] = reg[sl][i];
+      }
+    }
+  }
+  __syncthreads();
+  // thin Q = H_0 ... H_{r-1} [I; 0], accumulated backwards in the same registers
+#pragma unroll
+  for (int sl = 0; sl < CPW; ++sl) {
+    const int c = sl * 16 + wave;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) reg[sl][i] = (lane + 64 * i == c) ? 1.0 : 0.0;
+  }
+  for (int j = r - 1; j >= 0; --j) {
+    const double tj = tau[j];
+    if (tj == 0.0) continue;
+    double vr[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int row = lane + 64 * i;
+      vr[i] = (row >= j && row < m) ? X[(long)j * m + row] : 0.0;
+    }
+#pragma unroll
+    for (int sl = 0; sl < CPW; ++sl) {
+      const int c = sl * 16 + wave;
+      if (c >= j && c < r) {
+        double d = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) d += vr[i] * reg[sl][i];
+        d = wave_sum(d) * tj;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) reg[sl][i] -= d * vr[i];
+      }
+    }
+  }
+#pragma unroll
+  for (int sl = 0; sl < CPW; ++sl) {
+    const int c = sl * 16 + wave;
+    if (c < r) {
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int row = lane + 64 * i;
+        if (row < m) qstore(row, c, reg[sl][i]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// T[i * trs + j] = sum_t la(i, t) lb(t, j) for i < M, j < N on FP64 MFMA
+// (16 x 16 tiles, one per wave at a time; each K-chunk of 64 is loaded into
+// registers before its 16 MFMAs so the loads overlap). Any block size that is
+// a multiple of 64.
+template <class LA, class LB>
+__device__ void wg_gemm_f64(int M, int N, int K, LA la, LB lb, double* T, long trs) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tm = (M + 15) / 16, tn = (N + 15) / 16;
+  for (int t = wave; t < tm * tn; t += nw) {
+    const int m0 = (t / tn) * 16, n0 = (t % tn) * 16;
+    v4d acc = v4d{0, 0, 0, 0};
+    for (int kb = 0; kb < K; kb += 32) {
+      double a[8], b[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = kb + 4 * q + lk;
+        a[q] = (m0 + li < M && k < K) ? la(m0 + li, k) : 0.0;
+        b[q] = (k < K && n0 + li < N) ? lb(k, n0 + li) : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = m0 + lk + 4 * v, col = n0 + li;
+      if (row < M && col < N) T[(long)row * trs + col] = acc[v];
+    }
   }
 }
 

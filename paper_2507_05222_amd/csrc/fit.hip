@@ -59,7 +59,7 @@ struct FGeo {
 // per-chain workspace: for each term its environments, transposes and scratch
 struct FLay {
   size_t env[MAXT], LA[MAXT], RA[MAXT], Mt[MAXT], Mt2[MAXT], F1[MAXT], F2[MAXT];
-  size_t tmpA, gp, total;
+  size_t tmpA, gp, part, ctr, total;
   static FLay make(int L, int cy, const int* ck, int W, int nt) {
     FLay l;
     size_t o = 0;
@@ -76,6 +76,8 @@ struct FLay {
     }
     l.tmpA = o; o += al(4 * (size_t)cy * cy);
     l.gp = o; o += al(4 * 4 * (size_t)cy * cy);
+    l.part = o; o += al((size_t)SPLIT_SLOTS * TILE * TILE);
+    l.ctr = o; o += al(SPLIT_CTRS / 2);
     l.total = o;
     return l;
   }
@@ -103,7 +105,10 @@ __global__ void k_fit_transposes(FBatch fb, FGeo g, FLay l) {
 }
 
 __global__ void k_fit_env_init(FBatch fb, FGeo g, FLay l) {
-  if (blockIdx.x >= fb.n || threadIdx.x != 0) return;
+  if (blockIdx.x >= fb.n) return;
+  unsigned* ctr = reinterpret_cast<unsigned*>(fb.c[blockIdx.x].ws + l.ctr);
+  for (int i = threadIdx.x; i < SPLIT_CTRS; i += blockDim.x) ctr[i] = 0u;
+  if (threadIdx.x != 0) return;
   for (int t = 0; t < fb.nt; ++t) {
     fb.c[blockIdx.x].ws[l.LA[t]] = 1.0;
     fb.c[blockIdx.x].ws[l.RA[t] + (size_t)g.L * l.env[t]] = 1.0;
@@ -150,54 +155,70 @@ __global__ void k_fit_random(FBatch fb, FGeo g) {
 // Householder QR (left-to-right move, bond kept) and LQ (right-to-left move) of core k of y
 __global__ void __launch_bounds__(1024) k_fit_lr_qr(FBatch fb, FGeo g, FLay l) {
   extern __shared__ double smem[];
-  __shared__ double rdiag[512], tau[512];
+  __shared__ double rdiag[512], tau[512], vbuf[1024];
   if (blockIdx.x >= fb.n) return;
   const FChain& c = fb.c[blockIdx.x];
   const int k = g.k, cap = g.cy;
   const int m = 2 * c.yb[k], n = c.yb[k + 1];
   const int r = m < n ? m : n;
-  const size_t need = ((size_t)m * n + (size_t)m * r) * sizeof(double);
+  const bool fast = (m <= 256 && n <= 128);
+  const size_t need = ((size_t)m * n + (fast ? 0 : (size_t)m * r)) * sizeof(double);
   double* X = (need <= (size_t)g.lds) ? smem : (c.ws + l.gp);
-  double* Q = X + (size_t)m * n;
   double* Yk = c.y + (long)k * sl2(cap);
+  const int S = cap * 2 * cap;
   for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
     const int j = e / m, i = e % m;
     X[e] = Yk[(long)i * cap + j];
   }
   __syncthreads();
-  householder(X, m, n, rdiag, tau);
-  householder_q(X, m, n, tau, Q);
-  const int S = cap * 2 * cap;
-  for (int e = threadIdx.x; e < S; e += blockDim.x) {
-    const int i = e / cap, j = e % cap;
-    Yk[e] = (i < m && j < r) ? Q[(long)j * m + i] : 0.0;
+  if (fast) {
+    for (int e = threadIdx.x; e < S; e += blockDim.x) Yk[e] = 0.0;
+    auto qs = [&](int i, int j, double v) { Yk[(long)i * cap + j] = v; };
+    if (m <= 128 && n <= 64) qr_regs<2, 4>(X, m, n, rdiag, tau, vbuf, qs);
+    else qr_regs<4, 8>(X, m, n, rdiag, tau, vbuf, qs);
+  } else {
+    double* Q = X + (size_t)m * n;
+    householder(X, m, n, rdiag, tau);
+    householder_q(X, m, n, tau, Q);
+    for (int e = threadIdx.x; e < S; e += blockDim.x) {
+      const int i = e / cap, j = e % cap;
+      Yk[e] = (i < m && j < r) ? Q[(long)j * m + i] : 0.0;
+    }
   }
   if (threadIdx.x == 0) c.yb[k + 1] = r;
 }
 
 __global__ void __launch_bounds__(1024) k_fit_rl_lq(FBatch fb, FGeo g, FLay l) {
   extern __shared__ double smem[];
-  __shared__ double rdiag[512], tau[512];
+  __shared__ double rdiag[512], tau[512], vbuf[1024];
   if (blockIdx.x >= fb.n) return;
   const FChain& c = fb.c[blockIdx.x];
   const int k = g.k, cap = g.cy;
   const int nb = c.yb[k], mb = c.yb[k + 1];
   const int m = 2 * mb, n = nb, r = m < n ? m : n;
-  const size_t need = ((size_t)m * n + (size_t)m * r) * sizeof(double);
+  const bool fast = (m <= 256 && n <= 128);
+  const size_t need = ((size_t)m * n + (fast ? 0 : (size_t)m * r)) * sizeof(double);
   double* X = (need <= (size_t)g.lds) ? smem : (c.ws + l.gp);
-  double* Q = X + (size_t)m * n;
   double* Yk = c.y + (long)k * sl2(cap);
+  const int S = cap * 2 * cap;
   for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
     const int a = e / m, rho = e % m, s = rho / mb, bb = rho % mb;
     X[e] = Yk[(long)a * 2 * cap + s * cap + bb];
   }
   __syncthreads();
-  householder(X, m, n, rdiag, tau);
-  householder_q(X, m, n, tau, Q);
-  const int S = cap * 2 * cap;
-  for (int e = threadIdx.x; e < S; e += blockDim.x) {
-    const int j = e / (2 * cap), s = (e / cap) % 2, bb = e % cap;
-    Yk[e] = (j < r && bb < mb) ? Q[(long)j * m + s * mb + bb] : 0.0;
+  if (fast) {
+    for (int e = threadIdx.x; e < S; e += blockDim.x) Yk[e] = 0.0;
+    auto qs = [&](int rho, int j, double v) { Yk[(long)j * 2 * cap + (rho / mb) * cap + rho % mb] = v; };
+    if (m <= 128 && n <= 64) qr_regs<2, 4>(X, m, n, rdiag, tau, vbuf, qs);
+    else qr_regs<4, 8>(X, m, n, rdiag, tau, vbuf, qs);
+  } else {
+    double* Q = X + (size_t)m * n;
+    householder(X, m, n, rdiag, tau);
+    householder_q(X, m, n, tau, Q);
+    for (int e = threadIdx.x; e < S; e += blockDim.x) {
+      const int j = e / (2 * cap), s = (e / cap) % 2, bb = e % cap;
+      Yk[e] = (j < r && bb < mb) ? Q[(long)j * m + s * mb + bb] : 0.0;
+    }
   }
   if (threadIdx.x == 0) c.yb[k] = r;
 }
@@ -215,12 +236,13 @@ struct Fitter {
     j.alpha = 1.0; j.beta = 0.0;
   }
   // launch a list of jobs in groups of GB (one launch per group)
-  void run(std::vector<GemmJob>& jobs, int maxb, int maxM, int maxN, int m) {
+  void run(std::vector<GemmJob>& jobs, int maxb, int maxM, int maxN, int m, int ksplit = 1) {
     for (size_t i0 = 0; i0 < jobs.size(); i0 += GB) {
       GemmBatch gb;
       std::memset(&gb, 0, sizeof(gb));
       gb.n = (int)std::min<size_t>(GB, jobs.size() - i0);
       gb.maxb = maxb;
+      gb.ksplit = ksplit;
       for (int i = 0; i < gb.n; ++i) gb.j[i] = jobs[i0 + i];
       run_jobs(gb, maxM, maxN, m, s);
     }
@@ -269,9 +291,10 @@ struct Fitter {
         j.C = c.y + (size_t)k * g.cy * 2 * g.cy; j.crs = C_(g.cy); j.ccs = C_(1);
         j.M = B1(c.yb, k, 2); j.N = B1(c.yb, k + 1); j.K = B1(tm.ab, k + 1, ck);
         j.alpha = tm.coef; j.beta = (t == 0) ? 0.0 : 1.0;
+        j.part = c.ws + l.part; j.ctr = reinterpret_cast<unsigned*>(c.ws + l.ctr);
         d.push_back(j);
       }
-      run(d, 1, 2 * g.cy, g.cy, mode);
+      run(d, 1, 2 * g.cy, g.cy, mode, ksplit_for(2 * g.cy, g.cy, g.wcap[t] * g.ck[t]));
     }
   }
 

@@ -49,9 +49,10 @@ enum KClass {
   KC_ZIP_CARRY = 3,     // carry projection U^T Theta
   KC_RL_SVD = 4,        // right-to-left Jacobi SVD sweep sites
   KC_LR_QR = 5,         // Householder QR / LQ gauge moves
-  KC_JOBS = 6,          // environment / local-matvec / projection GEMMs
+  KC_JOBS = 6,          // environment / local-matvec / projection GEMMs, FP64 MFMA
   KC_CG = 7,            // local CG vector updates
-  KC_COUNT = 8
+  KC_JOBS_LP = 8,       // the same GEMMs on FP32 or BF16 MFMA
+  KC_COUNT = 9
 };
 
 namespace qttk {

@@ -667,7 +667,9 @@ void tmark(int kc, hipStream_t s) {
   Timer& t = timer();
   if (t.kc != kc) return;
   if (t.used >= t.ev.size()) {
-    if (t.ev.size() >= (size_t)1 << 17) return;          // cap: later launches are not recorded
+    // cap reached (always at a pair boundary: used is even here): stop timing this
+    // class altogether, so launches are neither recorded nor counted from now on
+    if (t.ev.size() >= (size_t)1 << 17) { t.kc = -1; return; }
     const size_t grow = t.ev.empty() ? 4096 : t.ev.size();
     for (size_t i = 0; i < grow; ++i) {
       hipEvent_t e;

@@ -52,7 +52,7 @@ struct SGeo {
 
 // workspace layout (doubles)
 struct SLay {
-  size_t LA, RA, Lb, Rb, F1, F2, F3, Mt, Mt2, beff, r, p, Ap, dinv, sc, tmpA, gp, total;
+  size_t LA, RA, Lb, Rb, F1, F2, F3, Mt, Mt2, beff, r, p, Ap, dinv, sc, tmpA, gp, part, ctr, total;
   size_t env, envb;
   static SLay make(int L, int cx, int ck, int cb, int W) {
     SLay l;
@@ -78,6 +78,8 @@ struct SLay {
     l.sc = o; o += 64;
     l.tmpA = o; o += al(4 * (size_t)cx * cx);
     l.gp = o; o += al(4 * 4 * (size_t)cx * cx);
+    l.part = o; o += al((size_t)SPLIT_SLOTS * TILE * TILE);
+    l.ctr = o; o += al(SPLIT_CTRS / 2);
     l.total = o;
     return l;
   }
@@ -117,6 +119,8 @@ __global__ void k_env_init(SBatch sb, SGeo g, SLay l) {
     c.ws[l.Rb + (size_t)g.L * l.envb] = 1.0;
   }
   if (threadIdx.x < S_COUNT) c.ws[l.sc + threadIdx.x] = 0.0;
+  unsigned* ctr = reinterpret_cast<unsigned*>(c.ws + l.ctr);
+  for (int i = threadIdx.x; i < SPLIT_CTRS; i += blockDim.x) ctr[i] = 0u;
 }
 
 // start of a sweep: clear the maximum of the projected residuals
@@ -201,96 +205,153 @@ __global__ void __launch_bounds__(1024) k_cg_init(SBatch sb, SGeo g, SLay l, int
   }
 }
 
+// Two sums over the workgroup with one pair of barriers.
+__device__ void block_sum2(double& u, double& v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  u = wave_sum(u);
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) { red[wave] = u; red[16 + wave] = v; }
+  __syncthreads();
+  double tu = 0.0, tv = 0.0;
+  for (int i = 0; i < nw; ++i) { tu += red[i]; tv += red[16 + i]; }
+  u = tu; v = tv;
+}
+
+// One preconditioned CG iteration of every chain (one workgroup per chain).
+// Up to 8 elements per thread (2 cx^2 <= 8192) all operands are loaded once, in
+// one round trip, and kept in registers through the three phases.
 __global__ void __launch_bounds__(1024) k_cg_step(SBatch sb, SGeo g, SLay l) {
-  __shared__ double red[16];
+  __shared__ double red[32];
   if (blockIdx.x >= sb.n) return;
   const SChain& c = sb.c[blockIdx.x];
-  double* sc = c.ws + l.sc;
-  if (sc[S_DONE] != 0.0) return;
-  const int k = g.k, cx = g.cx;
+  const gdp sc = as_global(c.ws + l.sc);
+  const double done0 = sc[S_DONE], rz = sc[S_RZ], it0 = sc[S_ITER], rn0 = sc[S_RN0];
+  if (done0 != 0.0) return;
+  const int k = g.k, cx = g.cx, n = 2 * cx * cx;
   const int nl = c.xb[k], nr = c.xb[k + 1];
-  double* x = c.x + (long)k * sl2(cx);
-  double* r = c.ws + l.r;
-  double* p = c.ws + l.p;
-  const double* Ap = c.ws + l.Ap;
-  const double* dinv = c.ws + l.dinv;
-  double pAp = 0;
-  for (int e = threadIdx.x; e < 2 * cx * cx; e += blockDim.x) pAp += p[e] * Ap[e];
-  pAp = block_sum(pAp, red);
-  const double rz = sc[S_RZ];
-  const double alpha = pAp > 0.0 ? rz / pAp : 0.0;
-  double rn = 0, rz2 = 0;
-  for (int e = threadIdx.x; e < 2 * cx * cx; e += blockDim.x) {
-    const int a = e / (2 * cx), cc = e % cx;
-    if (a < nl && cc < nr) {
-      x[e] += alpha * p[e];
-      const double rv = r[e] - alpha * Ap[e];
-      r[e] = rv;
-      rn += rv * rv;
-      rz2 += rv * dinv[e] * rv;
+  const gdp x = as_global(c.x + (long)k * sl2(cx));
+  const gdp r = as_global(c.ws + l.r);
+  const gdp p = as_global(c.ws + l.p);
+  const gcdp Ap = as_global((const double*)(c.ws + l.Ap));
+  const gcdp dinv = as_global((const double*)(c.ws + l.dinv));
+  const int tid = threadIdx.x;
+  double pAp = 0.0, rn = 0.0, rz2 = 0.0, alpha = 0.0;
+  bool done;
+  if (n <= 8 * 1024) {
+    double pv[8], av[8], xv[8], rv[8], dv[8];
+    bool ok[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = tid + 1024 * q;
+      const bool in = e < n;
+      ok[q] = in && (e / (2 * cx)) < nl && (e % cx) < nr;
+      pv[q] = in ? p[e] : 0.0;
+      av[q] = in ? Ap[e] : 0.0;
+      xv[q] = ok[q] ? x[e] : 0.0;
+      rv[q] = ok[q] ? r[e] : 0.0;
+      dv[q] = ok[q] ? dinv[e] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) pAp += pv[q] * av[q];
+    pAp = block_sum(pAp, red);
+    alpha = pAp > 0.0 ? rz / pAp : 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (ok[q]) {
+        const int e = tid + 1024 * q;
+        x[e] = xv[q] + alpha * pv[q];
+        rv[q] -= alpha * av[q];
+        r[e] = rv[q];
+        rn += rv[q] * rv[q];
+        rz2 += rv[q] * dv[q] * rv[q];
+      }
+    }
+    block_sum2(rn, rz2, red);
+    done = !(pAp > 0.0) || rn <= fmax(g.ltol * g.ltol * rn0, c.atol2) || it0 + 1.0 >= g.maxit;
+    if (!done) {
+      const double beta = rz > 0.0 ? rz2 / rz : 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (ok[q]) p[tid + 1024 * q] = dv[q] * rv[q] + beta * pv[q];
+    }
+  } else {
+    for (int e = tid; e < n; e += blockDim.x) pAp += p[e] * Ap[e];
+    pAp = block_sum(pAp, red);
+    alpha = pAp > 0.0 ? rz / pAp : 0.0;
+    for (int e = tid; e < n; e += blockDim.x) {
+      const int a = e / (2 * cx), cc = e % cx;
+      if (a < nl && cc < nr) {
+        x[e] += alpha * p[e];
+        const double v = r[e] - alpha * Ap[e];
+        r[e] = v;
+        rn += v * v;
+        rz2 += v * dinv[e] * v;
+      }
+    }
+    block_sum2(rn, rz2, red);
+    done = !(pAp > 0.0) || rn <= fmax(g.ltol * g.ltol * rn0, c.atol2) || it0 + 1.0 >= g.maxit;
+    if (!done) {
+      const double beta = rz > 0.0 ? rz2 / rz : 0.0;
+      for (int e = tid; e < n; e += blockDim.x) p[e] = dinv[e] * r[e] + beta * p[e];
     }
   }
-  rn = block_sum(rn, red);
-  rz2 = block_sum(rz2, red);
-  const double it = sc[S_ITER] + 1.0;
-  const bool done = !(pAp > 0.0) || rn <= fmax(g.ltol * g.ltol * sc[S_RN0], c.atol2) || it >= g.maxit;
-  if (!done) {
-    const double beta = rz > 0.0 ? rz2 / rz : 0.0;
-    for (int e = threadIdx.x; e < 2 * cx * cx; e += blockDim.x) p[e] = dinv[e] * r[e] + beta * p[e];
-  }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    sc[S_RZ] = rz2; sc[S_RN2] = rn; sc[S_ITER] = it;
+  if (tid == 0) {
+    sc[S_RZ] = rz2; sc[S_RN2] = rn; sc[S_ITER] = it0 + 1.0;
     sc[S_ITERS_TOTAL] += 1.0;
     sc[S_DONE] = done ? 1.0 : 0.0;
   }
 }
 
 // Right-to-left gauge move at site k by Householder LQ (bond kept):
-// Y_k (b_k x 2 b_{k+1}): Y_k^T = Q R  ->  core k <- Q^T, tmp <- Y_{k-1} R^T.
+// Y_k (b_k x 2 b_{k+1}): Y_k^T = Q R  ->  core k <- Q^T, Y_{k-1} <- Y_{k-1} R^T.
 __global__ void __launch_bounds__(1024) k_rl_qr(SBatch sb, SGeo g, SLay l) {
   extern __shared__ double smem[];
-  __shared__ double rdiag[512], tau[512];
+  __shared__ double rdiag[512], tau[512], vbuf[1024];
   if (blockIdx.x >= sb.n) return;
   const SChain& c = sb.c[blockIdx.x];
   const int k = g.k, cap = g.cx;
   const int nb = c.xb[k], mb = c.xb[k + 1];
   const int m = 2 * mb, n = nb, r = m < n ? m : n;
-  const size_t need = ((size_t)m * n + (size_t)m * r) * sizeof(double);
+  const bool fast = (m <= 256 && n <= 128);
+  const size_t need = ((size_t)m * n + (fast ? 0 : (size_t)m * r)) * sizeof(double);
   // The budget passed in smem size is checked by the host; fall back to global scratch otherwise.
   double* X = (need <= (size_t)g.lds) ? smem : (c.ws + l.gp);
-  double* Q = X + (size_t)m * n;
   double* Yk = c.x + (long)k * sl2(cap);
+  const int S = cap * 2 * cap;
   for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
     const int a = e / m, rho = e % m, s = rho / mb, bb = rho % mb;
     X[e] = Yk[(long)a * 2 * cap + s * cap + bb];
   }
   __syncthreads();
-  householder(X, m, n, rdiag, tau);
-  householder_q(X, m, n, tau, Q);
-  const int S = cap * 2 * cap;
-  for (int e = threadIdx.x; e < S; e += blockDim.x) {
-    const int j = e / (2 * cap), s = (e / cap) % 2, bb = e % cap;
-    Yk[e] = (j < r && bb < mb) ? Q[(long)j * m + s * mb + bb] : 0.0;
+  if (fast) {
+    for (int e = threadIdx.x; e < S; e += blockDim.x) Yk[e] = 0.0;
+    auto qs = [&](int rho, int j, double v) { Yk[(long)j * 2 * cap + (rho / mb) * cap + rho % mb] = v; };
+    if (m <= 128 && n <= 64) qr_regs<2, 4>(X, m, n, rdiag, tau, vbuf, qs);
+    else qr_regs<4, 8>(X, m, n, rdiag, tau, vbuf, qs);
+  } else {
+    double* Q = X + (size_t)m * n;
+    householder(X, m, n, rdiag, tau);
+    householder_q(X, m, n, tau, Q);
+    for (int e = threadIdx.x; e < S; e += blockDim.x) {
+      const int j = e / (2 * cap), s = (e / cap) % 2, bb = e % cap;
+      Yk[e] = (j < r && bb < mb) ? Q[(long)j * m + s * mb + bb] : 0.0;
+    }
   }
-  // Y_{k-1} <- Y_{k-1} R^T  (R: r x n upper trapezoidal; R^T: n x r)
+  // Y_{k-1} <- Y_{k-1} R^T  (R: r x n upper trapezoidal; R^T: n x r); rows (a0, s)
   const int np = c.xb[k - 1];
   double* Yp = c.x + (long)(k - 1) * sl2(cap);
   double* T = c.ws + l.tmpA;
   __syncthreads();
-  for (int e = threadIdx.x; e < S; e += blockDim.x) {
-    const int a0 = e / (2 * cap), s = (e / cap) % 2, j = e % cap;
-    double v = 0.0;
-    if (a0 < np && j < r) {
-      const double* yrow = Yp + (long)a0 * 2 * cap + s * cap;
-      // (Y R^T)[., j] = sum_t Y[., t] R[j][t], R[j][j] = rdiag, R[j][t>j] = X[t][j]
-      v = yrow[j] * rdiag[j];
-      for (int t = j + 1; t < n; ++t) v += yrow[t] * X[(long)t * m + j];
-    }
-    T[e] = v;
-  }
+  auto la = [&](int rho, int t) { return Yp[(long)rho * cap + t]; };
+  auto lb = [&](int t, int j) { return t == j ? rdiag[j] : (t > j ? X[(long)t * m + j] : 0.0); };
+  wg_gemm_f64(2 * np, r, n, la, lb, T, cap);
   __syncthreads();
-  for (int e = threadIdx.x; e < S; e += blockDim.x) Yp[e] = T[e];
+  for (int e = threadIdx.x; e < S; e += blockDim.x) {
+    const int a0 = e / (2 * cap), j = e % cap;
+    Yp[e] = (a0 < np && j < r) ? T[e] : 0.0;
+  }
   if (threadIdx.x == 0) c.xb[k] = r;
 }
 
@@ -298,43 +359,48 @@ __global__ void __launch_bounds__(1024) k_rl_qr(SBatch sb, SGeo g, SLay l) {
 // core k (2 b_k x b_{k+1}) = Q R -> core k <- Q, core k+1 <- R core k+1.
 __global__ void __launch_bounds__(1024) k_lr_qr_keep(SBatch sb, SGeo g, SLay l) {
   extern __shared__ double smem[];
-  __shared__ double rdiag[512], tau[512];
+  __shared__ double rdiag[512], tau[512], vbuf[1024];
   if (blockIdx.x >= sb.n) return;
   const SChain& c = sb.c[blockIdx.x];
   const int k = g.k, cap = g.cx;
   const int m = 2 * c.xb[k], n = c.xb[k + 1];
   const int r = m < n ? m : n;
-  const size_t need = ((size_t)m * n + (size_t)m * r) * sizeof(double);
+  const bool fast = (m <= 256 && n <= 128);
+  const size_t need = ((size_t)m * n + (fast ? 0 : (size_t)m * r)) * sizeof(double);
   double* X = (need <= (size_t)g.lds) ? smem : (c.ws + l.gp);
-  double* Q = X + (size_t)m * n;
   double* Yk = c.x + (long)k * sl2(cap);
+  const int S = cap * 2 * cap;
   for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
     const int j = e / m, i = e % m;
     X[e] = Yk[(long)i * cap + j];
   }
   __syncthreads();
-  householder(X, m, n, rdiag, tau);
-  householder_q(X, m, n, tau, Q);
-  const int S = cap * 2 * cap;
-  for (int e = threadIdx.x; e < S; e += blockDim.x) {
-    const int i = e / cap, j = e % cap;
-    Yk[e] = (i < m && j < r) ? Q[(long)j * m + i] : 0.0;
+  if (fast) {
+    for (int e = threadIdx.x; e < S; e += blockDim.x) Yk[e] = 0.0;
+    auto qs = [&](int i, int j, double v) { Yk[(long)i * cap + j] = v; };
+    if (m <= 128 && n <= 64) qr_regs<2, 4>(X, m, n, rdiag, tau, vbuf, qs);
+    else qr_regs<4, 8>(X, m, n, rdiag, tau, vbuf, qs);
+  } else {
+    double* Q = X + (size_t)m * n;
+    householder(X, m, n, rdiag, tau);
+    householder_q(X, m, n, tau, Q);
+    for (int e = threadIdx.x; e < S; e += blockDim.x) {
+      const int i = e / cap, j = e % cap;
+      Yk[e] = (i < m && j < r) ? Q[(long)j * m + i] : 0.0;
+    }
   }
-  const int n2 = c.xb[k + 2];
+  // core k+1 <- R core k+1: rows j < r, columns (s, bb) contiguous
   double* Yn = c.x + (long)(k + 1) * sl2(cap);
   double* T = c.ws + l.tmpA;
   __syncthreads();
-  for (int e = threadIdx.x; e < S; e += blockDim.x) {
-    const int j = e / (2 * cap), s = (e / cap) % 2, bb = e % cap;
-    double v = 0.0;
-    if (j < r && bb < n2) {
-      v = rdiag[j] * Yn[(long)j * 2 * cap + s * cap + bb];
-      for (int t = j + 1; t < n; ++t) v += X[(long)t * m + j] * Yn[(long)t * 2 * cap + s * cap + bb];
-    }
-    T[e] = v;
-  }
+  auto la = [&](int j, int t) { return t == j ? rdiag[j] : (t > j ? X[(long)t * m + j] : 0.0); };
+  auto lb = [&](int t, int nu) { return Yn[(long)t * 2 * cap + nu]; };
+  wg_gemm_f64(r, 2 * cap, n, la, lb, T, 2 * cap);
   __syncthreads();
-  for (int e = threadIdx.x; e < S; e += blockDim.x) Yn[e] = T[e];
+  for (int e = threadIdx.x; e < S; e += blockDim.x) {
+    const int j = e / (2 * cap);
+    Yn[e] = (j < r) ? T[e] : 0.0;
+  }
   if (threadIdx.x == 0) c.xb[k + 1] = r;
 }
 
@@ -449,7 +515,9 @@ struct Solver {
       d.B = c.ws + l.RA + (size_t)(k + 1) * l.env; d.brs = C_(1); d.bcs = B1(c.ab, k + 1, ck);
       d.C = c.x + (size_t)k * cx * 2 * cx; d.crs = C_(cx); d.ccs = C_(1);
       d.M = B1(c.xb, k, 2); d.N = B1(c.xb, k + 1); d.K = B1(c.ab, k + 1, ck);
+      d.part = c.ws + l.part; d.ctr = reinterpret_cast<unsigned*>(c.ws + l.ctr);
     }
+    g3.ksplit = ksplit_for(2 * cx, cx, W * ck);
     run_jobs(g3, 2 * cx, cx, mmode, s);
   }
 
@@ -545,7 +613,9 @@ struct Solver {
       d.C = c.ws + l.Ap; d.crs = C_(cx); d.ccs = C_(1);
       d.M = B1(c.xb, k, 2); d.N = B1(c.xb, k + 1); d.K = B1(c.ab, k + 1, cx);
       d.skip = skip;
+      d.part = c.ws + l.part; d.ctr = reinterpret_cast<unsigned*>(c.ws + l.ctr);
     }
+    g3.ksplit = ksplit_for(2 * cx, cx, W * cx);
     run_jobs(g1, cx * W, 2 * cx, mmode, s);
     run_jobs(g2, 2 * W, cx, mmode, s);
     run_jobs(g3, 2 * cx, cx, mmode, s);

@@ -11,8 +11,9 @@
 //
 // Every linear combination of products is one variational fit (Sec. 2.2,
 // qtt_fit) at the state's bond dimension; the two solves are the variational
-// ALS solver (qtt_poisson_solve). Independent chains run batched. After the first
-// step on a context the fits start from the previous step's results.
+// ALS solver (qtt_poisson_solve). Independent chains run batched. When the
+// previous step on this context advanced the same state (same u, v, p storage),
+// the fits start from that step's results, otherwise from a random sketch.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -24,8 +25,8 @@
 namespace qtt_solver_detail {
 double* step_pool(qtt_ctx* ctx, size_t doubles, int* rc);
 int set_error(qtt_ctx* ctx, int code, const char* msg);
-bool step_warm(qtt_ctx* ctx, int L, int cap);
-void set_step_warm(qtt_ctx* ctx, int L, int cap);
+bool step_warm(qtt_ctx* ctx, const void* const id[3], int L, int cap);
+void set_step_warm(qtt_ctx* ctx, const void* const id[3], int L, int cap);
 }
 
 namespace {
@@ -62,7 +63,9 @@ extern "C" int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_fl
   qtt_mpo DV{L, cap, diag_bonds.data(), ib + 64 * (NTMP + 1), pool + NTMP * slot + mslot};
 
   const int chi = std::min(o->trunc.chi_max, cap);
-  const bool warm = step_warm(ctx, L, cap);
+  // warm fits only when the temporaries come from the previous step of this state
+  const void* const sid[3] = {st->u.data, st->v.data, st->p.data};
+  const bool warm = step_warm(ctx, sid, L, cap);
   const int init = warm ? 0 : 1;
   const int sweeps = warm ? std::max(1, o->trunc.fit_sweeps) : std::max(2, o->trunc.fit_sweeps);
   const int mode = o->contract_dt;
@@ -143,6 +146,6 @@ extern "C" int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_fl
     qtt_mps y[2] = {st->u, st->v};
     if ((rc = qtt_fit(ctx, 2, 2, t, y, chi, sweeps, init, mode, stream))) return rc;
   }
-  set_step_warm(ctx, L, cap);
+  set_step_warm(ctx, sid, L, cap);
   return QTT_OK;
 }

@@ -46,23 +46,14 @@ class FlowState:
         return Q.CFlowState(self.u.desc(), self.v.desc(), self.p.desc())
 
 
-PRECISIONS = {
-    # derivative applies, Hadamard products, Helmholtz products, Poisson products
-    "f64": ("f64", "f64", "f64", "f64"),
-    "mixed": ("f32", "bf16", "bf16", "f32"),
-}
-
-
 def step_opts(dt, tol=1e-8, chi=64, dtype="f64", helm=None, pois=None, fit=2, product=None) -> Q.CStepOpts:
-    """dtype is the type of the derivative applies (or a PRECISIONS key); product that of
-    the Hadamard products (defaults to dtype)."""
-    if dtype in PRECISIONS:
-        d, prod, h, p = PRECISIONS[dtype]
-    else:
-        d, prod, h, p = dtype, product or dtype, dtype, dtype
-    helm = helm or Q.solve_opts(tol=1e-10, max_sweeps=4, max_local_iters=60, local_tol=1e-6, dtype=h)
-    pois = pois or Q.solve_opts(tol=1e-8, max_sweeps=8, max_local_iters=200, local_tol=1e-4, dtype=p)
-    return Q.CStepOpts(float(dt), Q.CTrunc(float(tol), int(chi), int(fit)), Q.DTYPES.get(d, d),
+    """dtype: contraction type of the fits (derivatives, right-hand sides, divergence,
+    projection); product: that of the Hadamard (convection) products, default dtype.
+    helm / pois: solver options (default: FP64 local products, tight tolerances)."""
+    prod = product or dtype
+    helm = helm or Q.solve_opts(tol=1e-10, max_sweeps=4, max_local_iters=80, local_tol=1e-2, dtype="f64")
+    pois = pois or Q.solve_opts(tol=1e-8, max_sweeps=8, max_local_iters=80, local_tol=1e-2, dtype="f64")
+    return Q.CStepOpts(float(dt), Q.CTrunc(float(tol), int(chi), int(fit)), Q.DTYPES.get(dtype, dtype),
                        Q.DTYPES.get(prod, prod), helm, pois)
 
 

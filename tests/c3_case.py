@@ -1,6 +1,6 @@
 """The 2^10 x 2^10 transient cylinder case (Re = 200, dt = 2e-3, chi = 64) run
 through the HIP fractional step and through the FD oracle from the same initial
-fields (uniform flow plus the App. E perturbation). Test infrastructure."""
+fields (uniform flow plus the App. G perturbation). Test infrastructure."""
 import numpy as np
 
 from oracle import diag, fd, qttref as R

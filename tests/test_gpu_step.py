@@ -21,3 +21,36 @@ def test_step_c1_bf16_contractions_within_budget():
     res, _ = run_c1(cap=32, dtype="f32", product_dtype="bf16", helm_dtype="bf16", pois_dtype="f32")
     for k in ("u", "v", "p"):
         assert res[k] < 3e-3, res
+
+
+def test_step_warm_start_is_per_state():
+    """A step of a state on a context that last advanced another state equals the
+    same step on a fresh context: the fits' warm start belongs to the state that
+    produced the context's intermediate trains, so both steps start cold.
+    Truncated bond (8 < full rank), where the start of a fit matters."""
+    import numpy as np
+    from paper_2507_05222_amd import flow as F, qtt as Q
+    from oracle import qttref as R
+    from qtt_inputs import noise_fields, random_mps_cores
+    n, cap, L = 5, 8, 10
+    perm = R.grid_perm(n, n)
+    ops = F.FlowOps(n, 20.0, 100.0, 1e-3)
+
+    def state(seed):
+        nz = noise_fields(n, n, 1e-2, seed=seed)
+        u = Q.tt_svd_host((1.0 + nz[0]).ravel()[perm], L, 0.0, cap, cap)
+        v = Q.tt_svd_host(nz[1].ravel()[perm], L, 0.0, cap, cap)
+        p = Q.MPS.from_cores(random_mps_cores(L, cap, seed=0), cap)
+        return F.FlowState(u, v, p)
+
+    opts = F.step_opts(1e-3, tol=1e-12, chi=cap, dtype="f64")
+    shared = Q.Context(0)
+    a, b = state(1), state(2)
+    F.fractional_step(shared, ops, a, opts)
+    F.fractional_step(shared, ops, b, opts)
+    b_ref = state(2)
+    F.fractional_step(Q.Context(0), ops, b_ref, opts)
+    for name in ("u", "v", "p"):
+        x = R.tt_full(getattr(b, name).cores())
+        y = R.tt_full(getattr(b_ref, name).cores())
+        assert np.linalg.norm(x - y) <= 1e-12 * np.linalg.norm(y), name
