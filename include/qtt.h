@@ -213,6 +213,15 @@ typedef struct {
   qtt_mps u, v, p;          /* current fields (right-canonical)                  */
 } qtt_flow_state;
 
+/* Learned warm start of the pressure solve (see the qtt_ws_* calls below). */
+typedef struct {
+  const float* params;      /* DEVICE, QTT_WS_NPARAMS floats                       */
+  double out_scale;         /* coarse pressure = output * out_scale * rms(coarse b) */
+  double re, alpha;         /* conditioning inputs: Reynolds number, rotation rate */
+  int32_t chi;              /* bond of the compressed coarse prediction, 1..cap    */
+  int32_t bf16;             /* network forward with BF16 operands                 */
+} qtt_ws_model;
+
 typedef struct {
   double dt;                /* time step                                          */
   qtt_trunc trunc;          /* truncation of every TT operation of the step       */
@@ -221,10 +230,15 @@ typedef struct {
   int32_t product_dt;       /* qtt_dtype of the convection (Hadamard) products    */
   qtt_solve_opts helmholtz; /* options of the two predictor solves                */
   qtt_solve_opts poisson;   /* options of the pressure solve                      */
+  const qtt_ws_model* warm; /* NULL, or the learned warm start of the pressure solve */
+  qtt_mps* rhs_out;         /* NULL, or receives the pressure right-hand side b   */
 } qtt_step_opts;
 
 typedef struct {
   qtt_solve_info helm_u, helm_v, poisson;
+  int32_t warm_used;        /* 1 if the learned guess replaced the previous pressure */
+  double warm_energy;       /* J at the optimal scale of the learned guess (0 if none) */
+  double prev_energy;       /* the same for the previous pressure                  */
 } qtt_step_info;
 
 /* One Chorin fractional step (Sec. 3.3): explicit convection (Hadamard products of
@@ -241,7 +255,16 @@ typedef struct {
  * qtt_fit at bond min(trunc.chi_max, cap) with trunc.fit_sweeps sweeps; the
  * context keeps the step's intermediate trains, and when the previous step on
  * the context advanced the same state (same u, v, p storage) the fits start
- * from them, otherwise from a random sketch (one more sweep). */
+ * from them, otherwise from a random sketch (one more sweep).
+ * With opts->warm (n >= 6 cores per axis, state->p.cap == state->u.cap): b is
+ * block-averaged to the 64 x 64 grid (its last 2(n-6) cores contracted with
+ * [1/2, 1/2]), the network predicts the coarse pressure, which is compressed by
+ * TT-SVD to bond warm->chi, prolonged piecewise constantly (2(n-6) appended
+ * cores [1, 1]) and fitted at the state's bond. Both candidates, the prediction
+ * and state->p, are rated at their optimal scale a* = b.x / x.Px by the solve's
+ * cost function J(x) = x.Px/2 - b.x (Sec. 2.1.4), J(a* x) = -(b.x)^2 / (2 x.Px);
+ * if the prediction rates lower, a* times it replaces state->p as the initial
+ * guess. opts->rhs_out (cap >= the state's bond) receives b. */
 int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_flow_state* state,
                         const qtt_step_opts* opts, qtt_step_info* info, void* stream);
 
@@ -295,6 +318,44 @@ int qtt_build_host(const qtt_cylinder* cyl, int which, int32_t cap, double* out,
  * cap*d*cap doubles (HOST) and bonds to bond_out (HOST int32[L+1]). */
 int qtt_tt_svd_host(const double* dense, int32_t L, int32_t d, const qtt_trunc* tr,
                     int32_t cap, double* out, int32_t* bond_out);
+
+/* ---- learned warm start of the pressure solve ------------------------------
+ * Not in the paper: its counterpart there is a TT preconditioner of the Poisson
+ * solve (App. G, Sec. 4.3). A four-layer 3x3 convolutional network maps
+ * (b, Re/200, alpha/2) on the 64 x 64 block-averaged grid (rows eta with zero
+ * padding, columns xi with periodic padding) to a coarse pressure, which the
+ * caller turns into an initial guess of qtt_poisson_solve. Channels 3 -> 32 ->
+ * 32 -> 32 -> 1, tanh after layers 1-3. All buffers are DEVICE float arrays,
+ * NCHW with H = W = 64, owned by the caller; calls are stream-ordered.
+ * Parameter layout: for layer l, w_l[co][ci][3][3] then b_l[co]. */
+#define QTT_WS_NPARAMS 19681
+#define QTT_WS_MSE_BLOCKS 64
+
+/* Floats of the activation buffer of a batch (the outputs of layers 1-3). */
+size_t qtt_ws_act_floats(int batch);
+/* Forward pass: in [batch][3][64][64] -> out [batch][1][64][64]; acts receives
+ * the layer outputs (qtt_ws_act_floats(batch) floats). bf16 != 0 rounds weights
+ * and layer inputs to BF16 (FP32 accumulation). batch 1..4096. */
+int qtt_ws_forward(qtt_ctx* ctx, const float* params, const float* in, int batch, float* acts, float* out,
+                   int bf16, void* stream);
+/* Backward pass of the FP32 forward with the same params/in/acts: gout is
+ * dL/d(out) ([batch][64][64], overwritten as scratch), grads (QTT_WS_NPARAMS
+ * floats) receives dL/d(params) (overwritten, not accumulated), scratch holds
+ * 2 * batch * 32 * 64 * 64 floats. Reductions run in a fixed order. */
+int qtt_ws_backward(qtt_ctx* ctx, const float* params, const float* in, int batch, float* acts, float* gout,
+                    float* grads, float* scratch, void* stream);
+/* Mean squared error over n values: gout = 2 (out - target) / n; partial
+ * (QTT_WS_MSE_BLOCKS floats) receives per-block sums of squared errors. */
+int qtt_ws_mse(qtt_ctx* ctx, const float* out, const float* target, int n, float* gout, float* partial,
+               void* stream);
+/* Block average of a train of L >= 12 binary cores in interleaved order onto
+ * the 64 x 64 grid (its last L - 12 cores contracted with [1/2, 1/2]): grid
+ * (HOST, 4096 doubles) receives [row eta][column xi]. Synchronises the stream. */
+int qtt_ws_coarse(qtt_ctx* ctx, const qtt_mps* x, double* grid, void* stream);
+/* One Adam step (Kingma & Ba, beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected,
+ * step >= 1) on QTT_WS_NPARAMS parameters; m and v are the moment buffers. */
+int qtt_ws_adam_step(qtt_ctx* ctx, float* params, const float* grads, float* m, float* v, int step, float lr,
+                     void* stream);
 
 #ifdef __cplusplus
 }

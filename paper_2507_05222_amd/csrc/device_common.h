@@ -192,6 +192,26 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
+// Maximum over the 64 lanes of a wavefront (same DPP pattern as wave_sum).
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_move<0x111>(v));
+  v = fmax(v, dpp_move<0x112>(v));
+  v = fmax(v, dpp_move<0x114>(v));
+  v = fmax(v, dpp_move<0x118>(v));
+  v = fmax(v, dpp_move<0x142>(v));
+  v = fmax(v, dpp_move<0x143>(v));
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), 63);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Columns whose largest entry is below this are treated as exactly zero by the
+// Householder factorisations (no reflector): the frame directions a rank-deficient
+// bond carries hold rounding noise that shrinks geometrically along a sweep, and
+// 1/|v|^2 of such a column would overflow.
+constexpr double HH_TINY = 1e-290;
+
 // One-sided Jacobi (Hestenes 1958) on the n columns of X (m rows; column j at
 // X + j*ldx), n <= 512. Rotations are accumulated into V (n x n, column j at
 // V + j*ldv) when V is not null. Parallel cyclic (round-robin) ordering: each round
@@ -326,19 +346,25 @@ __device__ void householder(double* X, int m, int n, double* rdiag, double* tau)
   for (int j = 0; j < r; ++j) {
     double* xj = X + (long)j * m;
     if (wave == 0) {
+      // scale-invariant reflector (see qr_regs): v = x / mx with v_j = x_j / mx - alpha
+      double mx = 0;
+      for (int i = j + lane; i < m; i += 64) mx = fmax(mx, fabs(xj[i]));
+      mx = wave_max(mx);
+      const bool live = mx > HH_TINY;
+      const double sc = live ? 1.0 / mx : 0.0;
       double s = 0;
-      for (int i = j + lane; i < m; i += 64) s += xj[i] * xj[i];
+      for (int i = j + lane; i < m; i += 64) s += (xj[i] * sc) * (xj[i] * sc);
       s = wave_sum(s);
-      const double x0 = xj[j];
+      const double x0 = xj[j] * sc;
+      for (int i = j + 1 + lane; i < m; i += 64) xj[i] *= sc;
       if (lane == 0) {
-        if (s == 0.0) { rdiag[j] = 0.0; tau[j] = 0.0; }
+        if (!live) { rdiag[j] = 0.0; tau[j] = 0.0; xj[j] = 0.0; }
         else {
           const double nrm = sqrt(s);
           const double alpha = x0 >= 0 ? -nrm : nrm;
           const double v0 = x0 - alpha;
-          const double vtv = s - x0 * x0 + v0 * v0;
-          rdiag[j] = alpha;
-          tau[j] = vtv > 0 ? 2.0 / vtv : 0.0;
+          rdiag[j] = alpha * mx;
+          tau[j] = 2.0 / (s - x0 * x0 + v0 * v0);
           xj[j] = v0;
         }
       }
@@ -394,34 +420,44 @@ __device__ void qr_regs(double* X, int m, int n, double* rdiag, double* tau, dou
         for (int sl = 0; sl < CPW; ++sl)
           if (sl == sj) col[i] = reg[sl][i];
       }
+      // reflector of the column scaled by its largest entry (scale-invariant, no
+      // underflow of |v|^2): H = I - tau v v^T with v = x / mx, v_j = x_j / mx - alpha
+      double mx = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int row = lane + 64 * i;
+        if (row >= j && row < m) mx = fmax(mx, fabs(col[i]));
+      }
+      mx = wave_max(mx);
+      const bool live = mx > HH_TINY;
+      const double sc = live ? 1.0 / mx : 0.0;
       double ss = 0.0, x0l = 0.0;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
         const int row = lane + 64 * i;
-        if (row >= j && row < m) ss += col[i] * col[i];
-        if (row == j) x0l = col[i];
+        if (row >= j && row < m) ss += (col[i] * sc) * (col[i] * sc);
+        if (row == j) x0l = col[i] * sc;
       }
       ss = wave_sum(ss);
       const double x0 = wave_sum(x0l);        // exactly one lane contributes
       double alpha = 0.0, v0 = 0.0, tj = 0.0;
-      if (ss > 0.0) {
+      if (live) {
         const double nrm = sqrt(ss);
         alpha = x0 >= 0 ? -nrm : nrm;
         v0 = x0 - alpha;
-        const double vtv = ss - x0 * x0 + v0 * v0;
-        tj = vtv > 0 ? 2.0 / vtv : 0.0;
+        tj = 2.0 / (ss - x0 * x0 + v0 * v0);
       }
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
         const int row = lane + 64 * i;
         if (row < m) {
-          const double v = (row < j) ? 0.0 : (row == j ? (ss > 0.0 ? v0 : col[i]) : col[i]);
+          const double v = (row < j || !live) ? 0.0 : (row == j ? v0 : col[i] * sc);
           vb[row] = v;
           // rows above j keep R's column j; rows from j on keep the reflector
           X[(long)j * m + row] = (row < j) ? col[i] : v;
         }
       }
-      if (lane == 0) { tau[j] = tj; rdiag[j] = alpha; }
+      if (lane == 0) { tau[j] = tj; rdiag[j] = alpha * mx; }
     }
     __syncthreads();
     const double tj = tau[j];

@@ -46,15 +46,25 @@ class FlowState:
         return Q.CFlowState(self.u.desc(), self.v.desc(), self.p.desc())
 
 
-def step_opts(dt, tol=1e-8, chi=64, dtype="f64", helm=None, pois=None, fit=2, product=None) -> Q.CStepOpts:
+def step_opts(dt, tol=1e-8, chi=64, dtype="f64", helm=None, pois=None, fit=2, product=None, warm=None,
+              rhs_out=None) -> Q.CStepOpts:
     """dtype: contraction type of the fits (derivatives, right-hand sides, divergence,
     projection); product: that of the Hadamard (convection) products, default dtype.
-    helm / pois: solver options (default: FP64 local products, tight tolerances)."""
+    helm / pois: solver options (default: FP64 local products, tight tolerances).
+    warm: a warmstart.WarmStart (learned initial guess of the pressure solve);
+    rhs_out: an MPS that receives the pressure right-hand side."""
     prod = product or dtype
     helm = helm or Q.solve_opts(tol=1e-10, max_sweeps=4, max_local_iters=80, local_tol=1e-2, dtype="f64")
     pois = pois or Q.solve_opts(tol=1e-8, max_sweeps=8, max_local_iters=80, local_tol=1e-2, dtype="f64")
-    return Q.CStepOpts(float(dt), Q.CTrunc(float(tol), int(chi), int(fit)), Q.DTYPES.get(dtype, dtype),
-                       Q.DTYPES.get(prod, prod), helm, pois)
+    o = Q.CStepOpts(float(dt), Q.CTrunc(float(tol), int(chi), int(fit)), Q.DTYPES.get(dtype, dtype),
+                    Q.DTYPES.get(prod, prod), helm, pois)
+    if warm is not None:
+        o._warm = warm.model()            # keep the struct alive with the options
+        o.warm = ctypes.pointer(o._warm)
+    if rhs_out is not None:
+        o._rhs = rhs_out.desc()
+        o.rhs_out = ctypes.pointer(o._rhs)
+    return o
 
 
 def fractional_step(ctx: Q.Context, ops: FlowOps, st: FlowState, opts: Q.CStepOpts, stream=None):

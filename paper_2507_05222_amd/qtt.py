@@ -71,13 +71,20 @@ class CFlowState(ctypes.Structure):
     _fields_ = [("u", CMps), ("v", CMps), ("p", CMps)]
 
 
+class CWsModel(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p), ("out_scale", ctypes.c_double), ("re", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("chi", ctypes.c_int32), ("bf16", ctypes.c_int32)]
+
+
 class CStepOpts(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("trunc", CTrunc), ("contract_dt", ctypes.c_int32),
-                ("product_dt", ctypes.c_int32), ("helmholtz", CSolveOpts), ("poisson", CSolveOpts)]
+                ("product_dt", ctypes.c_int32), ("helmholtz", CSolveOpts), ("poisson", CSolveOpts),
+                ("warm", ctypes.POINTER(CWsModel)), ("rhs_out", ctypes.POINTER(CMps))]
 
 
 class CStepInfo(ctypes.Structure):
-    _fields_ = [("helm_u", CSolveInfo), ("helm_v", CSolveInfo), ("poisson", CSolveInfo)]
+    _fields_ = [("helm_u", CSolveInfo), ("helm_v", CSolveInfo), ("poisson", CSolveInfo),
+                ("warm_used", ctypes.c_int32), ("warm_energy", ctypes.c_double), ("prev_energy", ctypes.c_double)]
 
 
 class CCylinder(ctypes.Structure):
@@ -117,6 +124,13 @@ def lib():
                                      p(ctypes.c_double)]
         L.qtt_build_host.argtypes = [p(CCylinder), i32, ctypes.c_int32, vp, vp, p(ctypes.c_int32)]
         L.qtt_tt_svd_host.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, p(CTrunc), ctypes.c_int32, vp, vp]
+        L.qtt_ws_act_floats.argtypes = [i32]
+        L.qtt_ws_act_floats.restype = ctypes.c_size_t
+        L.qtt_ws_forward.argtypes = [vp, vp, vp, i32, vp, vp, i32, vp]
+        L.qtt_ws_backward.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
+        L.qtt_ws_mse.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+        L.qtt_ws_adam_step.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_float, vp]
+        L.qtt_ws_coarse.argtypes = [vp, p(CMps), vp, vp]
         _lib = L
     return _lib
 

@@ -99,3 +99,23 @@ def test_fit_warm_start_and_batch(Q, ctx):
         opt = rel(R.tt_full(R.tt_svd(ref, L, chi_max=8)), ref)
         assert rel(R.tt_full(ys[i].cores()), ref) <= 1.5 * opt + 1e-12
         assert rel(R.tt_full(ys[i].cores()), first[i]) < 1e-2
+
+
+def test_fit_rank_deficient_target_stays_exact():
+    """A rank-1 train fitted at bond 32 over 16 cores: the frame directions beyond the
+    target's rank carry only rounding noise, which shrinks along the sweeps; the
+    Householder moves must keep them finite (scale-invariant reflectors)."""
+    import numpy as np
+    from paper_2507_05222_amd import qtt as Q
+    from oracle import qttref as R
+    rng = np.random.default_rng(5)
+    L, chi = 16, 32
+    cores = [rng.standard_normal((1, 2, 1)) for _ in range(L)]
+    x = Q.MPS.from_cores(cores, 2)
+    ref = R.tt_full(cores)
+    for sweeps in (1, 2, 3):
+        y = Q.MPS(L, chi)
+        Q.fit(Q.Context(0), [[(1.0, None, x)]], [y], chi=chi, sweeps=sweeps, init=1)
+        got = R.tt_full(y.cores())
+        assert np.isfinite(got).all(), sweeps
+        assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref), sweeps
