@@ -34,6 +34,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAKS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # dense TFLOP/s, MI355X published
+TRAFFIC = os.path.join(ROOT, "profiles", "k_gemm_jobs_f64_cylinder_2e20_chi64_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_05222_amd", "csrc", f) for f in ("gemm_jobs.h", "device_common.h")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_profile():
+    """From the committed rocprofv3 summaries of the dominant kernel: HBM bytes per
+    launch (--pmc FETCH_SIZE and WRITE_SIZE, scaled by what they read for a plain
+    copy) and the kernel-trace average duration; None when the kernel sources
+    changed since the counters were taken."""
+    try:
+        with open(TRAFFIC) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return {"traffic": 1024.0 * (t["fetch_kib_per_dispatch"] * t["fetch_factor"] +
+                                 t["write_kib_per_dispatch"] * t["write_factor"]),
+            "trace_avg_us": t.get("kernel_trace_avg_us")}
 
 
 def initial_fields(n, A0):
@@ -93,6 +121,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-lowp", action="store_true")
+    ap.add_argument("--no-warm", action="store_true", help="skip the learned-warm-start comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -145,6 +174,20 @@ def main():
         sps_l = args.steps / t_l
         fields["lowp"] = {k: dense(Q, F, getattr(st_l, k), n) for k in ("u", "v", "p")}
 
+    warm = None
+    if not args.no_warm and n == 10 and chi == 64:
+        # learned warm start vs cold start of the pressure solve on held-out (Re, alpha)
+        from paper_2507_05222_amd import warmstart as W
+        with open(os.path.join(W.DATA, "wsnet.json")) as f:
+            meta = json.load(f)
+        print("[bench] learned warm start vs cold start", file=sys.stderr, flush=True)
+        warm = {"held_out_rel_l2_coarse": meta["held_out_rel_l2"], "cases": []}
+        for re_, al in meta["test_configs"][:2]:
+            r = W.compare_cold_learned(ctx, re_, al)
+            warm["cases"].append({"Re": round(re_, 2), "alpha": round(al, 3),
+                                  "cold": {k: r["cold"][k] for k in ("cg_iters", "sweeps", "step_s")},
+                                  "learned": {k: r["learned"][k] for k in ("cg_iters", "sweeps", "step_s")}})
+
     cpu, errs = None, None
     if not args.no_cpu:
         # CPU baseline: the FP64 FD oracle on the same grid and initial field, the
@@ -171,10 +214,13 @@ def main():
     roof = None
     if kt["launches"] > 0 and kt["ms"] > 0:
         ach = kt["flops"] / (kt["ms"] * 1e-3) / 1e12
+        prof = measured_profile()
         roof = {"bound": "mfma", "achieved": round(ach, 4), "peak": PEAKS["f64"], "unit": "TFLOP/s",
-                "frac": round(ach / PEAKS["f64"], 6), "traffic": None,
+                "frac": round(ach / PEAKS["f64"], 6), "traffic": None if prof is None else round(prof["traffic"], 1),
                 "kernel": "k_gemm_jobs<0> (batched FP64 MFMA site/environment contractions)",
                 "avg_launch_us": round(1e3 * kt["ms"] / kt["launches"], 3), "launches": kt["launches"],
+                "timing": "HIP-event bracket per launch (includes its dispatch: an upper bound)",
+                "kernel_trace_avg_us": None if prof is None else prof["trace_avg_us"],
                 "flops_per_launch": round(kt["flops"] / kt["launches"], 1),
                 "bytes_per_launch": round(kt["bytes"] / kt["launches"], 1)}
 
@@ -207,6 +253,7 @@ def main():
                    "rel_l2_vs_oracle": errs,
                    "fast_solver": solver_summary(info_f),
                    "fp64_solver": None if info_p is None else solver_summary(info_p),
+                   "learned_warm_start": warm,
                    "setup_s": round(setup_s, 2)},
         "roofline": roof,
         "cpu_baseline": cpu,

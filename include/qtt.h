@@ -278,9 +278,12 @@ int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_flow_state* s
  * local-matvec / projection GEMMs on FP64 MFMA, 7 local CG updates, 8 the GEMMs
  * of class 6 on FP32 or BF16 MFMA; -1 stops timing.
  * qtt_timer_read synchronises the device and returns the number of timed
- * launches, their summed duration (ms) and the counted work. */
+ * launches, the summed duration of their event brackets (ms), the counted work,
+ * and, for reference, the mean duration of the same bracket around an empty
+ * launch on an idle stream (ms). A bracket holds the launch's dispatch besides
+ * the kernel, so ms / launches bounds the kernel's own duration from above. */
 int qtt_timer_start(qtt_ctx* ctx, int kernel_class);
-int qtt_timer_read(qtt_ctx* ctx, int64_t* launches, double* ms, double* flops, double* bytes);
+int qtt_timer_read(qtt_ctx* ctx, int64_t* launches, double* ms, double* flops, double* bytes, double* overhead_ms);
 
 /* ---- host-side operator construction (setup, FP64, no GPU) ----------------
  * Builds, on the host, the TT cores of the operators and boundary vectors of a

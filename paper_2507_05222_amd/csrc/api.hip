@@ -539,8 +539,9 @@ extern "C" int qtt_timer_start(qtt_ctx* ctx, int kernel_class) {
   return QTT_OK;
 }
 
-extern "C" int qtt_timer_read(qtt_ctx* ctx, int64_t* launches, double* ms, double* flops, double* bytes) {
-  if (!ctx || !launches || !ms || !flops || !bytes) return QTT_EINVAL;
+extern "C" int qtt_timer_read(qtt_ctx* ctx, int64_t* launches, double* ms, double* flops, double* bytes,
+                              double* overhead_ms) {
+  if (!ctx || !launches || !ms || !flops || !bytes || !overhead_ms) return QTT_EINVAL;
   qttk::Timer& t = qttk::timer();
   HIPCHK(ctx, hipDeviceSynchronize());
   double total = 0.0;
@@ -555,6 +556,7 @@ extern "C" int qtt_timer_read(qtt_ctx* ctx, int64_t* launches, double* ms, doubl
   *ms = total;
   *flops = c[0];
   *bytes = c[1];
+  *overhead_ms = qttk::bracket_overhead_ms(nullptr);
   t.kc = -1;
   return QTT_OK;
 }

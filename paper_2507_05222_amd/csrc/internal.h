@@ -65,6 +65,8 @@ struct Timer {
 Timer& timer();
 // Records an event on s if class kc is being timed (call before and after a launch).
 void tmark(int kc, hipStream_t s);
+// Mean duration (ms) of an event bracket around an empty launch on s.
+double bracket_overhead_ms(hipStream_t s);
 // Device counter pointer for a launch of class kc (null unless kc is being timed).
 inline double* tcount(int kc) { return timer().kc == kc ? timer().cnt : nullptr; }
 }  // namespace qttk

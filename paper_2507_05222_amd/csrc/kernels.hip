@@ -663,6 +663,30 @@ Timer& timer() {
   static Timer t;
   return t;
 }
+// Duration of an HIP-event bracket around an empty launch on stream s (ms): the
+// fixed cost of the two event packets and the dispatch, which every bracketed
+// launch of the timer also pays.
+__global__ void k_nop() {}
+double bracket_overhead_ms(hipStream_t s) {
+  constexpr int R = 64;
+  hipEvent_t e[2 * R];
+  for (auto& x : e) if (hipEventCreate(&x) != hipSuccess) return 0.0;
+  for (int i = 0; i < R; ++i) {
+    (void)hipEventRecord(e[2 * i], s);
+    hipLaunchKernelGGL(k_nop, dim3(1), dim3(64), 0, s);
+    (void)hipEventRecord(e[2 * i + 1], s);
+  }
+  (void)hipEventSynchronize(e[2 * R - 1]);
+  double tot = 0.0;
+  for (int i = 0; i < R; ++i) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e[2 * i], e[2 * i + 1]);
+    tot += ms;
+  }
+  for (auto& x : e) (void)hipEventDestroy(x);
+  return tot / R;
+}
+
 void tmark(int kc, hipStream_t s) {
   Timer& t = timer();
   if (t.kc != kc) return;

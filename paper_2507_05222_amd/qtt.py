@@ -121,7 +121,7 @@ def lib():
         L.qtt_fit.argtypes = [vp, i32, i32, p(CTerm), p(CMps), i32, i32, i32, i32, vp]
         L.qtt_timer_start.argtypes = [vp, i32]
         L.qtt_timer_read.argtypes = [vp, p(ctypes.c_int64), p(ctypes.c_double), p(ctypes.c_double),
-                                     p(ctypes.c_double)]
+                                     p(ctypes.c_double), p(ctypes.c_double)]
         L.qtt_build_host.argtypes = [p(CCylinder), i32, ctypes.c_int32, vp, vp, p(ctypes.c_int32)]
         L.qtt_tt_svd_host.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, p(CTrunc), ctypes.c_int32, vp, vp]
         L.qtt_ws_act_floats.argtypes = [i32]
@@ -415,8 +415,9 @@ class KernelTimer:
 
     def read(self):
         n = ctypes.c_int64(0)
-        ms, fl, by = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+        ms, fl, by, ov = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
         self.ctx.check(lib().qtt_timer_read(self.ctx.h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl),
-                                            ctypes.byref(by)))
-        return {"name": self.name, "dtype": self.dtype, "launches": int(n.value), "ms": ms.value,
-                "flops": fl.value, "bytes": by.value}
+                                            ctypes.byref(by), ctypes.byref(ov)))
+        launches = int(n.value)
+        return {"name": self.name, "dtype": self.dtype, "launches": launches, "ms": ms.value,
+                "idle_bracket_ms": ov.value, "flops": fl.value, "bytes": by.value}
