@@ -95,6 +95,44 @@ def dense(Q, F, m, n):
     return grid.reshape(N, N)
 
 
+def sweep(args):
+    """Isolated kernel sweep: random MPS (L = 24, cores N(0, 1/chi)) times random MPO
+    (bond w, entries N(0, 1)), zip-up apply plus rounding to chi, `trials` chains per
+    call. Reports the site-contraction kernels (k_zip_t1, k_zip_t2) in TFLOP/s from the
+    library's work counters and HIP-event brackets, and the whole apply time."""
+    import torch
+    from paper_2507_05222_amd import qtt as Q
+    from qtt_inputs import random_mps_cores, random_mpo_cores
+    L = 24
+    ctx = Q.Context(0)
+    for chi in [int(c) for c in args.sweep_chi.split(",")]:
+        xs = [Q.MPS.from_cores(random_mps_cores(L, chi, seed=100 + t), chi) for t in range(args.trials)]
+        for w in [int(v) for v in args.sweep_w.split(",")]:
+            Ms = [Q.MPO.from_cores(random_mpo_cores(L, w, seed=200 + t)) for t in range(args.trials)]
+            ys = [Q.MPS(L, chi) for _ in range(args.trials)]
+            for dt in args.sweep_dtypes.split(","):
+                Q.apply_mpo(ctx, Ms, xs, ys, tol=0.0, chi=chi, dtype=dt, fit=0)      # warm-up
+                torch.cuda.synchronize()
+                timer = Q.KernelTimer(ctx, "zip_contract", dt)
+                timer.start()
+                t0 = time.perf_counter()
+                Q.apply_mpo(ctx, Ms, xs, ys, tol=0.0, chi=chi, dtype=dt, fit=0)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                kt = timer.read()
+                tf = kt["flops"] / (kt["ms"] * 1e-3) / 1e12 if kt["ms"] > 0 else 0.0
+                print(json.dumps({"sweep": "apply+round", "L": L, "chi": chi, "w": w, "dtype": dt, "trials": args.trials,
+                                  "apply_ms": round(1e3 * wall, 3),
+                                  "contract_tflops": round(tf, 3), "contract_frac_of_peak": round(tf / PEAKS[dt], 5),
+                                  "contract_launches": kt["launches"],
+                                  "contract_avg_us": round(1e3 * kt["ms"] / max(kt["launches"], 1), 2),
+                                  "contract_gflop": round(kt["flops"] / 1e9, 3),
+                                  "contract_hbm_gb_s_alg": round(kt["bytes"] / (kt["ms"] * 1e-3) / 1e9, 1) if kt["ms"] > 0 else None}),
+                      flush=True)
+            del Ms, ys
+            torch.cuda.empty_cache()
+
+
 def run_path(Q, F, ctx, ops, U0, V0, P0, opts, warmup, steps):
     import torch
     st = F.FlowState(clone(Q, U0), clone(Q, V0), clone(Q, P0))
@@ -122,10 +160,20 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-lowp", action="store_true")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned-warm-start comparison")
+    ap.add_argument("--sweep", action="store_true",
+                    help="isolated MPO x MPS apply + round sweep instead of the step benchmark (one JSON line per shape)")
+    ap.add_argument("--sweep-chi", default="64,128,256")
+    ap.add_argument("--sweep-w", default="5,15,30")
+    ap.add_argument("--sweep-dtypes", default="f64,f32,bf16")
+    ap.add_argument("--trials", type=int, default=32, help="independent chains per apply call in the sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+
+    if args.sweep:
+        sweep(args)
+        return
 
     import torch
     from paper_2507_05222_amd import flow as F, qtt as Q

@@ -316,6 +316,21 @@ typedef struct {
 int qtt_build_host(const qtt_cylinder* cyl, int which, int32_t cap, double* out,
                    int32_t* bond_out, int32_t* need);
 
+/* ---- diagnostics (Sec. 4, App. C, App. F) --------------------------------- */
+
+/* Rows of a field in interleaved order (App. C: the eta bits of the row index
+ * are fixed, the remaining train over the xi bits is contracted): out (HOST,
+ * nrows * 2^(L/2) doubles) receives row rows[r] (0 <= rows[r] < 2^(L/2), 0 = the
+ * first interior row next to the wall) at out + r * 2^(L/2). Synchronises the stream. */
+int qtt_read_rows(qtt_ctx* ctx, const qtt_mps* x, int nrows, const int32_t* rows, double* out, void* stream);
+
+/* Drag and lift coefficients (App. F, Eq. liftdrag; rho = U = D = 1) of the
+ * cylinder cyl from rows (HOST, 5 * 2^n doubles): u on rows 0 and 1, v on rows 0
+ * and 1, p on row 0 (row 0 next to the wall), with the wall velocity of Eq.
+ * rot_bc. Stress tau = -(p + 2/(3Re) div v) I + (1/Re)(grad v + grad v^T), wall
+ * derivatives one-sided second order in eta, central in xi; host FP64. */
+int qtt_forces_host(const qtt_cylinder* cyl, const double* rows, double* cd, double* cl);
+
 /* Host TT-SVD of a dense vector of d^L doubles (App. D; same truncation rule as
  * qtt_trunc), used to encode initial fields. Writes cores into slots of
  * cap*d*cap doubles (HOST) and bonds to bond_out (HOST int32[L+1]). */

@@ -441,3 +441,44 @@ extern "C" int qtt_tt_svd_host(const double* dense, int32_t L, int32_t d, const 
   HostTT T = tt_svd_host(v, L, d, tr->rel_tol, std::min<int>(tr->chi_max, cap), 0.0);
   return write_mps(T, cap, out, bond_out, nullptr);
 }
+
+// Wall forces of App. F (drag and lift coefficients, rho = U = D = 1, Eq. liftdrag)
+// from the first two interior rows of u and v, the first of p, and the prescribed
+// wall velocity (Eq. rot_bc): tau = -(p + 2/(3Re) div v) I + (1/Re)(grad v + grad v^T),
+// force = sum_j tau n_j (D/2) 2 pi d_xi with n = (cos, sin) into the fluid; wall
+// derivatives one-sided second order in eta (rows -1, 0, 1), central in xi along
+// the wall, mapped with the row -1 metric terms.
+extern "C" int qtt_forces_host(const qtt_cylinder* cyl, const double* rows, double* cd, double* cl) {
+  if (!cyl || !rows || !cd || !cl || cyl->n < 2 || cyl->n > 14 || !(cyl->Re > 0.0)) return QTT_EINVAL;
+  const Grid g(cyl->n, cyl->r_out);
+  const int N = g.N;
+  const double* u0 = rows;
+  const double* u1 = rows + N;
+  const double* v0 = rows + 2 * N;
+  const double* v1 = rows + 3 * N;
+  const double* p0 = rows + 4 * N;
+  std::vector<double> uw(N), vw(N);
+  for (int j = 0; j < N; ++j) { uw[j] = cyl->alpha * std::sin(g.th[j]); vw[j] = -cyl->alpha * std::cos(g.th[j]); }
+  auto grad = [&](const std::vector<double>& fw, const double* f0, const double* f1, int j, double* fx, double* fz) {
+    const double fxi = (fw[(j + 1) % N] - fw[(j + N - 1) % N]) / (2.0 * g.dxi);
+    const double feta = (-3.0 * fw[j] + 4.0 * f0[j] - f1[j]) / (2.0 * g.deta);
+    const double J = g.at(g.J, -1, j);
+    *fx = (g.at(g.z_eta, -1, j) * fxi - g.at(g.z_xi, -1, j) * feta) / J;
+    *fz = (-g.at(g.x_eta, -1, j) * fxi + g.at(g.x_xi, -1, j) * feta) / J;
+  };
+  const double Re = cyl->Re, ds = g.r[1] * 2.0 * M_PI * g.dxi;    // r[1] is row -1: the wall, D/2
+  double Fx = 0.0, Fz = 0.0;
+  for (int j = 0; j < N; ++j) {
+    double ux, uz, vx, vz;
+    grad(uw, u0, u1, j, &ux, &uz);
+    grad(vw, v0, v1, j, &vx, &vz);
+    const double div = ux + vz, pres = p0[j] + 2.0 / (3.0 * Re) * div;
+    const double t11 = -pres + 2.0 / Re * ux, t22 = -pres + 2.0 / Re * vz, t12 = (uz + vx) / Re;
+    const double c = std::cos(g.th[j]), s = std::sin(g.th[j]);
+    Fx += (t11 * c + t12 * s) * ds;
+    Fz += (t12 * c + t22 * s) * ds;
+  }
+  *cd = 2.0 * Fx;
+  *cl = 2.0 * Fz;
+  return QTT_OK;
+}

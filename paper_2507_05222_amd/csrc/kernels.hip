@@ -544,8 +544,8 @@ void mpo_transpose(const Batch& b, const Geo& g, hipStream_t s) {
 
 void zip_t1(const Batch& b, const Geo& g, hipStream_t s) {
   Geo gg = g;
-  gg.cnt = tcount(KC_ZIP_CONTRACT);
   tmark(KC_ZIP_CONTRACT, s);
+  gg.cnt = tcount(KC_ZIP_CONTRACT);
   dim3 grid(cdiv(2 * g.capx, TILE), cdiv(g.capy * g.W, TILE), b.n);
   const WsLayout wl = lay(g);
   if (g.mode == 0) hipLaunchKernelGGL(k_zip_t1<0>, grid, dim3(256), 0, s, b, gg, wl);
@@ -556,8 +556,8 @@ void zip_t1(const Batch& b, const Geo& g, hipStream_t s) {
 
 void zip_t2(const Batch& b, const Geo& g, hipStream_t s) {
   Geo gg = g;
-  gg.cnt = tcount(KC_ZIP_CONTRACT);
   tmark(KC_ZIP_CONTRACT, s);
+  gg.cnt = tcount(KC_ZIP_CONTRACT);
   dim3 grid(cdiv(g.capx, TILE), cdiv(2 * g.W, TILE), b.n * g.capy);
   const WsLayout wl = lay(g);
   if (g.mode == 0) hipLaunchKernelGGL(k_zip_t2<0>, grid, dim3(256), 0, s, b, gg, wl);
@@ -568,8 +568,8 @@ void zip_t2(const Batch& b, const Geo& g, hipStream_t s) {
 
 void zip_gram(const Batch& b, const Geo& g, hipStream_t s) {
   Geo gg = g;
-  gg.cnt = tcount(KC_ZIP_GRAM);
   tmark(KC_ZIP_GRAM, s);
+  gg.cnt = tcount(KC_ZIP_GRAM);
   dim3 grid(cdiv(2 * g.capy, TILE), cdiv(2 * g.capy, TILE), b.n * g.splits);
   hipLaunchKernelGGL(k_zip_gram, grid, dim3(256), 0, s, b, gg, lay(g));
   tmark(KC_ZIP_GRAM, s);
@@ -577,16 +577,16 @@ void zip_gram(const Batch& b, const Geo& g, hipStream_t s) {
 
 void zip_factor(const Batch& b, const Geo& g, hipStream_t s) {
   Geo gg = g;
-  gg.cnt = tcount(KC_ZIP_FACTOR);
   tmark(KC_ZIP_FACTOR, s);
+  gg.cnt = tcount(KC_ZIP_FACTOR);
   hipLaunchKernelGGL(k_zip_factor, dim3(b.n), dim3(FACT_THREADS), g.lds, s, b, gg, lay(g));
   tmark(KC_ZIP_FACTOR, s);
 }
 
 void zip_carry(const Batch& b, const Geo& g, hipStream_t s) {
   Geo gg = g;
-  gg.cnt = tcount(KC_ZIP_CARRY);
   tmark(KC_ZIP_CARRY, s);
+  gg.cnt = tcount(KC_ZIP_CARRY);
   dim3 grid(cdiv(g.W * g.capx, TILE), cdiv(g.capy, TILE), b.n);
   hipLaunchKernelGGL(k_zip_carry, grid, dim3(256), 0, s, b, gg, lay(g));
   tmark(KC_ZIP_CARRY, s);
@@ -598,8 +598,8 @@ void zip_last(const Batch& b, const Geo& g, hipStream_t s) {
 
 void rl_svd_site(const Batch& b, const Geo& g, int from_tmp, hipStream_t s) {
   Geo gg = g;
-  gg.cnt = tcount(KC_RL_SVD);
   tmark(KC_RL_SVD, s);
+  gg.cnt = tcount(KC_RL_SVD);
   hipLaunchKernelGGL(k_rl_svd, dim3(b.n), dim3(FACT_THREADS), g.lds, s, b, gg, lay(g), from_tmp);
   tmark(KC_RL_SVD, s);
 }
@@ -610,8 +610,8 @@ void rl_finish(const Batch& b, const Geo& g, hipStream_t s) {
 
 void lr_qr_site(const Batch& b, const Geo& g, int from_tmp, hipStream_t s) {
   Geo gg = g;
-  gg.cnt = tcount(KC_LR_QR);
   tmark(KC_LR_QR, s);
+  gg.cnt = tcount(KC_LR_QR);
   hipLaunchKernelGGL(k_lr_qr, dim3(b.n), dim3(FACT_THREADS), g.lds, s, b, gg, lay(g), from_tmp);
   tmark(KC_LR_QR, s);
 }

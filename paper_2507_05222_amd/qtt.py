@@ -131,6 +131,8 @@ def lib():
         L.qtt_ws_mse.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         L.qtt_ws_adam_step.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_float, vp]
         L.qtt_ws_coarse.argtypes = [vp, p(CMps), vp, vp]
+        L.qtt_read_rows.argtypes = [vp, p(CMps), i32, vp, vp, vp]
+        L.qtt_forces_host.argtypes = [p(CCylinder), vp, p(ctypes.c_double), p(ctypes.c_double)]
         _lib = L
     return _lib
 

@@ -17,8 +17,9 @@ def solve_opts_for(dtype):
     return helm, pois
 
 
-def run(nsteps, n=N_CORES, chi=CHI, dtype="f64", product=None):
-    """Per-step eps_L2 of (u, v, p) against the oracle and the solver infos."""
+def run(nsteps, n=N_CORES, chi=CHI, dtype="f64", product=None, return_state=False):
+    """Per-step eps_L2 of (u, v, p) against the oracle and the solver infos (and, with
+    return_state, the final TT state, the oracle's last stage dict, the context and ops)."""
     from paper_2507_05222_amd import flow as F, qtt as Q
     L = 2 * n
     g = OGrid(n, n)
@@ -44,4 +45,6 @@ def run(nsteps, n=N_CORES, chi=CHI, dtype="f64", product=None):
             grid[perm] = R.tt_full(m.cores())
             errs[name] = diag.eps_l2(g, grid, ref[name])
         out.append((errs, info))
+    if return_state:
+        return out, st, ref, ctx, ops
     return out

@@ -1,0 +1,32 @@
+"""The library's wall-force computation (qtt_forces_host, host FP64) against the
+oracle's (oracle/diag.py, pinned by closed forms) on the same dense fields: an FD
+step of the rotating cylinder on the 2^5 x 2^5 grid. No GPU."""
+import ctypes
+
+import numpy as np
+
+
+def test_forces_host_matches_oracle():
+    from oracle import diag, fd
+    from oracle.grid import OGrid
+    from paper_2507_05222_amd import qtt as Q
+    from qtt_inputs import noise_fields
+    n, Re, dt, alpha = 5, 100.0, 1e-3, 0.7
+    g = OGrid(n, n)
+    S = fd.FDSolver(g, Re, dt, alpha=alpha)
+    nz = noise_fields(n, n, 1e-2, seed=3)
+    u, v = 1.0 + nz[0].ravel(), nz[1].ravel()
+    for _ in range(2):
+        st = S.step(u, v, return_stages=True)
+        u, v = st["u"], st["v"]
+    p = st["p"]
+    bc = fd.velocity_bc(g, alpha)
+    cd_o, cl_o = diag.forces(g, u, v, p, Re, bc["u_wall"], bc["v_wall"])
+    N = 2 ** n
+    U, V, P = u.reshape(N, N), v.reshape(N, N), p.reshape(N, N)
+    rows = np.ascontiguousarray(np.concatenate([U[0], U[1], V[0], V[1], P[0]]))
+    cyl = Q.cylinder(n, 20.0, Re, dt, alpha)
+    cd, cl = ctypes.c_double(0), ctypes.c_double(0)
+    assert Q.lib().qtt_forces_host(ctypes.byref(cyl), rows.ctypes.data, ctypes.byref(cd), ctypes.byref(cl)) == 0
+    assert abs(cd.value - cd_o) <= 1e-12 * abs(cd_o) and abs(cl.value - cl_o) <= 1e-12 * max(abs(cl_o), 1e-3), \
+        (cd.value, cd_o, cl.value, cl_o)

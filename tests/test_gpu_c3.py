@@ -12,3 +12,23 @@ def test_c3_fp64_steps_match_oracle():
         # FD step up to the solver tolerances (1e-9) and FP64 rounding
         assert errs["u"] < 1e-6 and errs["v"] < 1e-6 and errs["p"] < 1e-5, (s, errs)
         assert info.poisson.residual < 1e-7, (s, info.poisson.residual)
+
+
+def test_c3_wall_forces_match_oracle():
+    """Drag and lift from the library's row read-out (App. C) and force formula
+    (App. F) on the TT state against the oracle's forces on its FD fields."""
+    from oracle import diag, fd
+    from oracle.grid import OGrid
+    from paper_2507_05222_amd import diag as D
+    from tests.c3_case import N_CORES, RE, run
+    _, st, ref, ctx, ops = run(2, return_state=True)
+    g = OGrid(N_CORES, N_CORES)
+    bc = fd.velocity_bc(g, 0.0)
+    cd_o, cl_o = diag.forces(g, ref["u"], ref["v"], ref["p"], RE, bc["u_wall"], bc["v_wall"])
+    cd, cl = D.forces(ctx, ops.cyl, st.u, st.v, st.p)
+    assert abs(cd - cd_o) <= 1e-6 * abs(cd_o), (cd, cd_o)
+    assert abs(cl - cl_o) <= 1e-6 * abs(cd_o), (cl, cl_o)
+    rows = D.read_rows(ctx, st.u, [0, 5, 2 ** N_CORES - 1])
+    import numpy as np
+    U = np.asarray(ref["u"]).reshape(2 ** N_CORES, 2 ** N_CORES)
+    assert np.abs(rows - U[[0, 5, 2 ** N_CORES - 1]]).max() < 1e-8
