@@ -113,24 +113,88 @@ def sweep(args):
             for dt in args.sweep_dtypes.split(","):
                 Q.apply_mpo(ctx, Ms, xs, ys, tol=0.0, chi=chi, dtype=dt, fit=0)      # warm-up
                 torch.cuda.synchronize()
-                timer = Q.KernelTimer(ctx, "zip_contract", dt)
-                timer.start()
-                t0 = time.perf_counter()
-                Q.apply_mpo(ctx, Ms, xs, ys, tol=0.0, chi=chi, dtype=dt, fit=0)
-                torch.cuda.synchronize()
-                wall = time.perf_counter() - t0
-                kt = timer.read()
-                tf = kt["flops"] / (kt["ms"] * 1e-3) / 1e12 if kt["ms"] > 0 else 0.0
-                print(json.dumps({"sweep": "apply+round", "L": L, "chi": chi, "w": w, "dtype": dt, "trials": args.trials,
-                                  "apply_ms": round(1e3 * wall, 3),
-                                  "contract_tflops": round(tf, 3), "contract_frac_of_peak": round(tf / PEAKS[dt], 5),
-                                  "contract_launches": kt["launches"],
-                                  "contract_avg_us": round(1e3 * kt["ms"] / max(kt["launches"], 1), 2),
-                                  "contract_gflop": round(kt["flops"] / 1e9, 3),
-                                  "contract_hbm_gb_s_alg": round(kt["bytes"] / (kt["ms"] * 1e-3) / 1e9, 1) if kt["ms"] > 0 else None}),
-                      flush=True)
+                rec = {"sweep": "apply+round", "L": L, "chi": chi, "w": w, "dtype": dt, "trials": args.trials}
+                for cls, tag in (("zip_contract", "carry_x_core"), ("zip_mpo", "x_mpo_core")):
+                    timer = Q.KernelTimer(ctx, cls, dt)
+                    timer.start()
+                    t0 = time.perf_counter()
+                    Q.apply_mpo(ctx, Ms, xs, ys, tol=0.0, chi=chi, dtype=dt, fit=0)
+                    torch.cuda.synchronize()
+                    rec["apply_ms"] = round(1e3 * (time.perf_counter() - t0), 3)
+                    kt = timer.read()
+                    tf = kt["flops"] / (kt["ms"] * 1e-3) / 1e12 if kt["ms"] > 0 else 0.0
+                    rec[tag] = {"tflops": round(tf, 3), "frac_of_peak": round(tf / PEAKS[dt], 5),
+                                "launches": kt["launches"], "avg_us": round(1e3 * kt["ms"] / max(kt["launches"], 1), 2),
+                                "gflop": round(kt["flops"] / 1e9, 3),
+                                "alg_gb_s": round(kt["bytes"] / (kt["ms"] * 1e-3) / 1e9, 1) if kt["ms"] > 0 else None}
+                a, b = rec["carry_x_core"], rec["x_mpo_core"]
+                tot_ms = (a["launches"] * a["avg_us"] + b["launches"] * b["avg_us"]) * 1e-3
+                tf = (a["gflop"] + b["gflop"]) / max(tot_ms, 1e-9)
+                rec["contraction"] = {"tflops": round(tf, 3), "frac_of_peak": round(tf / PEAKS[dt], 5)}
+                print(json.dumps(rec), flush=True)
             del Ms, ys
             torch.cuda.empty_cache()
+
+
+def steady(args):
+    """Steady cylinder flow, Re = 40, O-grid 2^8 x 2^8 (16 cores), chi = 32, dt = 5e-3:
+    the same run with FP64 and with FP32-MFMA contractions (fits and Hadamard
+    products; FP64 solves), drag and lift from the library's diagnostics. The
+    CPU-baseline leg runs the FD oracle over the same steps; its fields and forces
+    score both runs."""
+    import torch
+    from paper_2507_05222_amd import diag as D, flow as F, qtt as Q
+    from qtt_inputs import random_mps_cores
+    n, chi, Re, dt, K = 8, 32, 40.0, 5e-3, args.steady_steps
+    L = 2 * n
+    ctx = Q.Context(0)
+    ops = F.FlowOps(n, 20.0, Re, dt)
+    u0, v0 = initial_fields(n, 1e-2)
+    so = lambda tol: Q.solve_opts(tol=tol, max_sweeps=8, max_local_iters=80, local_tol=1e-2, dtype="f64")
+    res = {}
+    for name, dtype in (("fp64", "f64"), ("fp32", "f32")):
+        st = F.FlowState(Q.tt_svd_host(F.grid_to_qtt_order(u0), L, 1e-14, chi, chi),
+                         Q.tt_svd_host(F.grid_to_qtt_order(v0), L, 1e-14, chi, chi),
+                         Q.MPS.from_cores(random_mps_cores(L, chi, seed=0), chi))
+        opts = F.step_opts(dt, tol=1e-8, chi=chi, dtype=dtype, product=dtype, helm=so(1e-8), pois=so(1e-7))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist = []
+        for s_ in range(K):
+            F.fractional_step(ctx, ops, st, opts)
+            if (s_ + 1) % 100 == 0:
+                hist.append(D.forces(ctx, ops.cyl, st.u, st.v, st.p))
+                print(f"[bench] steady {name} step {s_ + 1}/{K} C_D {hist[-1][0]:.5f} C_L {hist[-1][1]:.2e}",
+                      file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        res[name] = {"steps_per_s": round(K / (time.perf_counter() - t0), 3),
+                     "C_D": hist[-1][0], "C_L": hist[-1][1],
+                     "fields": {k: dense(Q, F, getattr(st, k), n) for k in ("u", "v", "p")}}
+    cpu = None
+    if not args.no_cpu:
+        from oracle import diag, fd
+        from oracle.grid import OGrid
+        g = OGrid(n, n)
+        S = fd.FDSolver(g, Re, dt, solver="fft")
+        u, v = u0.ravel().copy(), v0.ravel().copy()
+        t1 = time.perf_counter()
+        for s_ in range(K):
+            ref = S.step(u, v, return_stages=True)
+            u, v = ref["u"], ref["v"]
+        tc = time.perf_counter() - t1
+        bc = fd.velocity_bc(g, 0.0)
+        cd, cl = diag.forces(g, ref["u"], ref["v"], ref["p"], Re, bc["u_wall"], bc["v_wall"])
+        cpu = {"value": round(K / tc, 3), "unit": "steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"{K} FD steps on the same 2^{n}x2^{n} grid", "C_D": cd, "C_L": cl}
+        for r in res.values():
+            f = r["fields"]
+            r["eps_l2_vs_oracle"] = {k: diag.eps_l2(g, f[k].ravel(), ref[k]) for k in ("u", "v", "p")}
+            r["C_D_rel_err"] = abs(r["C_D"] - cd) / abs(cd)
+            r["C_L_abs_err"] = abs(r["C_L"] - cl)
+    for r in res.values():
+        r.pop("fields")
+    print(json.dumps({"workload": f"steady cylinder Re={Re:g}, O-grid 2^{n}x2^{n}, chi={chi}, dt={dt:g}, {K} steps",
+                      "paths": res, "cpu_baseline": cpu}), flush=True)
 
 
 def run_path(Q, F, ctx, ops, U0, V0, P0, opts, warmup, steps):
@@ -166,6 +230,9 @@ def main():
     ap.add_argument("--sweep-w", default="5,15,30")
     ap.add_argument("--sweep-dtypes", default="f64,f32,bf16")
     ap.add_argument("--trials", type=int, default=32, help="independent chains per apply call in the sweep")
+    ap.add_argument("--steady", action="store_true",
+                    help="steady cylinder Re=40 on 2^8 x 2^8, chi 32: FP64 vs FP32-MFMA contractions, forces vs the oracle")
+    ap.add_argument("--steady-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -173,6 +240,9 @@ def main():
 
     if args.sweep:
         sweep(args)
+        return
+    if args.steady:
+        steady(args)
         return
 
     import torch

@@ -276,7 +276,8 @@ int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_flow_state* s
  * Gram products, 2 zip-up Jacobi factorisation, 3 zip-up carry projection,
  * 4 right-to-left Jacobi SVD sites, 5 Householder QR/LQ moves, 6 environment /
  * local-matvec / projection GEMMs on FP64 MFMA, 7 local CG updates, 8 the GEMMs
- * of class 6 on FP32 or BF16 MFMA; -1 stops timing.
+ * of class 6 on FP32 or BF16 MFMA, 9 zip-up contraction with the MPO core (class
+ * 0 is then the carry-times-core product alone); -1 stops timing.
  * qtt_timer_read synchronises the device and returns the number of timed
  * launches, the summed duration of their event brackets (ms), the counted work,
  * and, for reference, the mean duration of the same bracket around an empty

@@ -32,8 +32,9 @@ struct GemmJob {
   IE nb, sa, sb, sc;        // batch count and batch strides
   const double* skip;       // if non-null and *skip != 0, the job is skipped
   double alpha, beta;       // C = alpha A B + beta C
-  double* part;             // split-K: raw partial tiles (ksplit * tiles * 64 * 64)
-  unsigned* ctr;            // split-K: one arrival counter per output tile, zero between launches
+  double* part;             // split-K: raw partial tiles ([tile][split][64][64])
+  unsigned* ctr;            // split-K: one arrival counter per output tile, zero between launches;
+                            // null: partials only, C is not written (the consumer adds them)
 };
 struct GemmBatch {
   int n, maxb;
@@ -62,6 +63,17 @@ __global__ void __launch_bounds__(256) k_gemm_jobs(GemmBatch gb) {
   View B{j.B + (long)bi * ev(j.sb), ev(j.brs), ev(j.bcs)};
   if (S == 1) {
     gemm_tile<MODE>(M, N, 0, K, A, B, j.C + (long)bi * ev(j.sc), ev(j.crs), ev(j.ccs), j.alpha, j.beta, m0, n0);
+    return;
+  }
+  // Split-K without arrival counters: raw partial tiles only, summed in split order
+  // by the consuming kernel (the kernel boundary orders the accesses).
+  constexpr int BKr = Cfg<MODE>::BK;
+  if (!j.ctr) {
+    const int tile = blockIdx.y * gridDim.x + blockIdx.x;
+    const int kc = ((K + S - 1) / S + BKr - 1) / BKr * BKr;
+    const int k0 = min(K, sp * kc), k1 = min(K, k0 + kc);
+    double* P = j.part + ((size_t)tile * S + sp) * TILE * TILE;
+    gemm_tile<MODE>(M, N, k0, k1, A, B, P - ((long)m0 * TILE + n0), TILE, 1, 1.0, 0.0, m0, n0);
     return;
   }
   // Split-K: each split writes its raw partial tile; the last split to arrive

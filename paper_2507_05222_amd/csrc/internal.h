@@ -52,7 +52,8 @@ enum KClass {
   KC_JOBS = 6,          // environment / local-matvec / projection GEMMs, FP64 MFMA
   KC_CG = 7,            // local CG vector updates
   KC_JOBS_LP = 8,       // the same GEMMs on FP32 or BF16 MFMA
-  KC_COUNT = 9
+  KC_ZIP_MPO = 9,       // zip-up contraction with the MPO core (k_zip_t2)
+  KC_COUNT = 10
 };
 
 namespace qttk {

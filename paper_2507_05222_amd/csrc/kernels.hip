@@ -556,14 +556,14 @@ void zip_t1(const Batch& b, const Geo& g, hipStream_t s) {
 
 void zip_t2(const Batch& b, const Geo& g, hipStream_t s) {
   Geo gg = g;
-  tmark(KC_ZIP_CONTRACT, s);
-  gg.cnt = tcount(KC_ZIP_CONTRACT);
+  tmark(KC_ZIP_MPO, s);
+  gg.cnt = tcount(KC_ZIP_MPO);
   dim3 grid(cdiv(g.capx, TILE), cdiv(2 * g.W, TILE), b.n * g.capy);
   const WsLayout wl = lay(g);
   if (g.mode == 0) hipLaunchKernelGGL(k_zip_t2<0>, grid, dim3(256), 0, s, b, gg, wl);
   else if (g.mode == 1) hipLaunchKernelGGL(k_zip_t2<1>, grid, dim3(256), 0, s, b, gg, wl);
   else hipLaunchKernelGGL(k_zip_t2<2>, grid, dim3(256), 0, s, b, gg, wl);
-  tmark(KC_ZIP_CONTRACT, s);
+  tmark(KC_ZIP_MPO, s);
 }
 
 void zip_gram(const Batch& b, const Geo& g, hipStream_t s) {

@@ -48,11 +48,12 @@ struct SGeo {
   double ltol;      // local CG: reduction of the initial local residual
   int maxit;        // CG iterations per local problem
   int lds;          // dynamic LDS budget (bytes) of the gauge-move kernels
+  int mvs, mvtx;    // local matvec: K-splits of its last product and its tiles per row
 };
 
 // workspace layout (doubles)
 struct SLay {
-  size_t LA, RA, Lb, Rb, F1, F2, F3, Mt, Mt2, beff, r, p, Ap, dinv, sc, tmpA, gp, part, ctr, total;
+  size_t LA, RA, Lb, Rb, F1, F2, F3, Mt, Mt2, beff, r, p, Ap, dinv, sc, tmpA, gp, part, ctr, LM, total;
   size_t env, envb;
   static SLay make(int L, int cx, int ck, int cb, int W) {
     SLay l;
@@ -80,6 +81,7 @@ struct SLay {
     l.gp = o; o += al(4 * 4 * (size_t)cx * cx);
     l.part = o; o += al((size_t)SPLIT_SLOTS * TILE * TILE);
     l.ctr = o; o += al(SPLIT_CTRS / 2);
+    l.LM = o; o += al((size_t)cx * 2 * W * 2 * cx);
     l.total = o;
     return l;
   }
@@ -166,6 +168,18 @@ __device__ double block_sum(double v, double* red) {
   return t;
 }
 
+// Element e = (a 2 + s) cx + c of the local product M_eff v: the split-K partial
+// tiles of its last GEMM added in split order (or the product itself, unsplit).
+__device__ __forceinline__ double ap_at(const SChain& c, const SGeo& g, const SLay& l, int e) {
+  if (g.mvs <= 1) return c.ws[l.Ap + e];
+  const int row = e / g.cx, col = e % g.cx;
+  const int tile = (row >> 6) * g.mvtx + (col >> 6), within = (row & 63) * 64 + (col & 63);
+  const double* P = c.ws + l.part + (size_t)tile * g.mvs * 4096 + within;
+  double v = 0.0;
+  for (int q = 0; q < g.mvs; ++q) v += P[(size_t)q * 4096];
+  return v;
+}
+
 // first != 0: the residual belongs to the iterate before this local update; it is
 // recorded as the reference of the relative stop and in the sweep maximum.
 __global__ void __launch_bounds__(1024) k_cg_init(SBatch sb, SGeo g, SLay l, int first) {
@@ -176,7 +190,6 @@ __global__ void __launch_bounds__(1024) k_cg_init(SBatch sb, SGeo g, SLay l, int
   const int nl = c.xb[k], nr = c.xb[k + 1];
   double* sc = c.ws + l.sc;
   const double* beff = c.ws + l.beff;
-  const double* Ax = c.ws + l.Ap;
   double* r = c.ws + l.r;
   double* p = c.ws + l.p;
   const double* dinv = c.ws + l.dinv;
@@ -185,7 +198,7 @@ __global__ void __launch_bounds__(1024) k_cg_init(SBatch sb, SGeo g, SLay l, int
     const int a = e / (2 * cx), cc = e % cx;
     double rv = 0, pv = 0;
     if (a < nl && cc < nr) {
-      rv = beff[e] - Ax[e];
+      rv = beff[e] - ap_at(c, g, l, e);
       pv = dinv[e] * rv;
       rz += rv * pv; bn += beff[e] * beff[e]; rn += rv * rv;
     }
@@ -233,7 +246,6 @@ __global__ void __launch_bounds__(1024) k_cg_step(SBatch sb, SGeo g, SLay l) {
   const gdp x = as_global(c.x + (long)k * sl2(cx));
   const gdp r = as_global(c.ws + l.r);
   const gdp p = as_global(c.ws + l.p);
-  const gcdp Ap = as_global((const double*)(c.ws + l.Ap));
   const gcdp dinv = as_global((const double*)(c.ws + l.dinv));
   const int tid = threadIdx.x;
   double pAp = 0.0, rn = 0.0, rz2 = 0.0, alpha = 0.0;
@@ -247,7 +259,7 @@ __global__ void __launch_bounds__(1024) k_cg_step(SBatch sb, SGeo g, SLay l) {
       const bool in = e < n;
       ok[q] = in && (e / (2 * cx)) < nl && (e % cx) < nr;
       pv[q] = in ? p[e] : 0.0;
-      av[q] = in ? Ap[e] : 0.0;
+      av[q] = ok[q] ? ap_at(c, g, l, e) : 0.0;
       xv[q] = ok[q] ? x[e] : 0.0;
       rv[q] = ok[q] ? r[e] : 0.0;
       dv[q] = ok[q] ? dinv[e] : 0.0;
@@ -276,14 +288,17 @@ __global__ void __launch_bounds__(1024) k_cg_step(SBatch sb, SGeo g, SLay l) {
         if (ok[q]) p[tid + 1024 * q] = dv[q] * rv[q] + beta * pv[q];
     }
   } else {
-    for (int e = tid; e < n; e += blockDim.x) pAp += p[e] * Ap[e];
+    for (int e = tid; e < n; e += blockDim.x) {
+      const int a = e / (2 * cx), cc = e % cx;
+      if (a < nl && cc < nr) pAp += p[e] * ap_at(c, g, l, e);
+    }
     pAp = block_sum(pAp, red);
     alpha = pAp > 0.0 ? rz / pAp : 0.0;
     for (int e = tid; e < n; e += blockDim.x) {
       const int a = e / (2 * cx), cc = e % cx;
       if (a < nl && cc < nr) {
         x[e] += alpha * p[e];
-        const double v = r[e] - alpha * Ap[e];
+        const double v = r[e] - alpha * ap_at(c, g, l, e);
         r[e] = v;
         rn += v * v;
         rz2 += v * dinv[e] * v;
@@ -586,38 +601,51 @@ struct Solver {
     run_jobs(g2, 2 * cx, cx, 0, s);
   }
 
-  // out = M_eff v at site k (v, out: [a][s][c], row stride cx)
+  // LM[(a, s', b')][(a', s)] = sum_b LA_k[a][b][a'] A_k[b][s'][s][b'] (left environment
+  // times the MPO core), once per local problem: the local product is then two GEMMs.
+  void build_lm(int k) {
+    const int cx = g.cx, W = g.W;
+    for (int i = 0; i < 2; ++i) {
+      GemmBatch gb = batch(cx);
+      for (int q = 0; q < sb.n; ++q) {
+        const SChain& c = sb.c[q];
+        GemmJob& j = gb.j[q]; one(j);    // per a: LM_a[(s',b')][a'] (input index s = i) = Mt_i[(s',b')][b] LA_a[b][a']
+        j.A = c.ws + l.Mt + (size_t)k * 4 * W * W + i; j.ars = B1(c.ab, k, 2); j.acs = C_(2);
+        j.B = c.ws + l.LA + (size_t)k * l.env; j.brs = C_(cx); j.bcs = C_(1);
+        j.C = c.ws + l.LM + i; j.crs = C_(2 * cx); j.ccs = C_(2);
+        j.M = B1(c.ab, k + 1, 2); j.N = B1(c.xb, k); j.K = B1(c.ab, k);
+        j.nb = B1(c.xb, k); j.sb = B1(c.ab, k, cx); j.sc = B1(c.ab, k + 1, 4 * cx);
+      }
+      run_jobs(gb, 2 * W, cx, 0, s);
+    }
+  }
+
+  // out = M_eff v at site k (v, out: [a][s][c], row stride cx): T = LM v, then
+  // out = T RA, the last product split over K into raw partial tiles (g.mvs > 1)
+  // that the CG kernels add.
   void matvec(int k, bool v_is_x, int mmode) {
     const int cx = g.cx, W = g.W;
-    GemmBatch g1 = batch(1), g2 = batch(cx), g3 = batch(1);
+    GemmBatch g1 = batch(1), g3 = batch(1);
     for (int i = 0; i < sb.n; ++i) {
       const SChain& c = sb.c[i];
       const double* v = v_is_x ? (c.x + (size_t)k * cx * 2 * cx) : (c.ws + l.p);
       const double* skip = v_is_x ? nullptr : (c.ws + l.sc + S_DONE);
-      GemmJob& a = g1.j[i]; one(a);    // T[(a,b)][(s,c')] = LA[(a,b)][a'] v[a'][(s,c')]
-      a.A = c.ws + l.LA + (size_t)k * l.env; a.ars = C_(cx); a.acs = C_(1);
-      a.B = v; a.brs = C_(2 * cx); a.bcs = C_(1);
-      a.C = c.ws + l.F1; a.crs = C_(2 * cx); a.ccs = C_(1);
-      a.M = B2(c.xb, k, c.ab, k); a.N = C_(2 * cx); a.K = B1(c.xb, k);
+      GemmJob& a = g1.j[i]; one(a);    // T[(a,s',b')][c'] = LM[(a,s',b')][(a',s)] v[(a',s)][c']
+      a.A = c.ws + l.LM; a.ars = C_(2 * cx); a.acs = C_(1);
+      a.B = v; a.brs = C_(cx); a.bcs = C_(1);
+      a.C = c.ws + l.F2; a.crs = C_(cx); a.ccs = C_(1);
+      a.M = B2(c.xb, k, c.ab, k + 1, 2); a.N = C_(cx); a.K = B1(c.xb, k, 2);
       a.skip = skip;
-      GemmJob& b = g2.j[i]; one(b);    // U[a][(s',b')][c'] = Mt[(s',b')][(b,s)] T[a][(b,s)][c']
-      b.A = c.ws + l.Mt + (size_t)k * 4 * W * W; b.ars = B1(c.ab, k, 2); b.acs = C_(1);
-      b.B = c.ws + l.F1; b.brs = C_(cx); b.bcs = C_(1);
-      b.C = c.ws + l.F2; b.crs = C_(cx); b.ccs = C_(1);
-      b.M = B1(c.ab, k + 1, 2); b.N = C_(cx); b.K = B1(c.ab, k, 2);
-      b.nb = B1(c.xb, k); b.sb = B1(c.ab, k, 2 * cx); b.sc = B1(c.ab, k + 1, 2 * cx);
-      b.skip = skip;
-      GemmJob& d = g3.j[i]; one(d);    // out[(a,s')][c] = U[(a,s')][(b',c')] RA[c][(b',c')]
+      GemmJob& d = g3.j[i]; one(d);    // out[(a,s')][c] = T[(a,s')][(b',c')] RA[c][(b',c')]
       d.A = c.ws + l.F2; d.ars = B1(c.ab, k + 1, cx); d.acs = C_(1);
       d.B = c.ws + l.RA + (size_t)(k + 1) * l.env; d.brs = C_(1); d.bcs = B1(c.ab, k + 1, cx);
       d.C = c.ws + l.Ap; d.crs = C_(cx); d.ccs = C_(1);
       d.M = B1(c.xb, k, 2); d.N = B1(c.xb, k + 1); d.K = B1(c.ab, k + 1, cx);
       d.skip = skip;
-      d.part = c.ws + l.part; d.ctr = reinterpret_cast<unsigned*>(c.ws + l.ctr);
+      if (g.mvs > 1) { d.part = c.ws + l.part; d.ctr = nullptr; }
     }
-    g3.ksplit = ksplit_for(2 * cx, cx, W * cx);
-    run_jobs(g1, cx * W, 2 * cx, mmode, s);
-    run_jobs(g2, 2 * W, cx, mmode, s);
+    g3.ksplit = g.mvs;
+    run_jobs(g1, cx * 2 * W, cx, mmode, s);
     run_jobs(g3, 2 * cx, cx, mmode, s);
   }
 
@@ -634,6 +662,7 @@ struct Solver {
     SGeo gg = g;
     gg.k = k;
     beff(k);
+    build_lm(k);
     hipLaunchKernelGGL(k_precond, dim3(8, sb.n), dim3(256), 0, s, sb, gg, l);
     const int reps = (mmode == 0) ? 1 : 4;
     const int per = std::max(1, g.maxit / reps);
@@ -741,6 +770,8 @@ extern "C" int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qt
       c.ws = ws + lay.total * i;
     }
     S.g = SGeo{L, 0, cx, cb, wcap, W, cx, opts->local_tol, opts->max_local_iters, lds};
+    S.g.mvs = ksplit_for(2 * cx, cx, W * cx);
+    S.g.mvtx = cdiv(cx, TILE);
     S.l = lay;
     S.mode = opts->contract_dt;
     S.s = s;
@@ -858,6 +889,8 @@ int fit_sweeps(qtt_ctx* ctx, int n, const qtt_mpo* M, const qtt_mps* x, qtt_mps*
       c.ws = ws + lay.total * i;
     }
     S.g = SGeo{L, 0, cx, 1, wcap, W, ck, 0.0, 0, lds_of(ctx)};
+    S.g.mvs = 1;
+    S.g.mvtx = 1;
     S.l = lay;
     S.mode = mode;
     S.s = s;

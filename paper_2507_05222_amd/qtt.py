@@ -402,7 +402,8 @@ def tt_svd_host(dense: np.ndarray, L: int, tol: float, chi: int, cap: int, devic
 # measurement hook
 # ---------------------------------------------------------------------------
 KERNEL_CLASSES = {"zip_contract": 0, "zip_gram": 1, "zip_factor": 2, "zip_carry": 3, "rl_svd": 4,
-                  "qr_moves": 5, "env_gemm": 6, "cg_update": 7, "env_gemm_lowp": 8}
+                  "qr_moves": 5, "env_gemm": 6, "cg_update": 7, "env_gemm_lowp": 8,
+                  "zip_mpo": 9}
 
 
 class KernelTimer:
