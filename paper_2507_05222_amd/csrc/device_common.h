@@ -53,7 +53,9 @@ __device__ __forceinline__ typename Cfg<MODE>::T to_t(double v) {
 // The K loop keeps the next K-block's global loads in flight (in registers)
 // while the MFMAs of the current block run from LDS: with the small grids of
 // the bond-dimension GEMMs the tile time is dominated by load latency.
-template <int MODE>
+// ATOM: the tile is added to C with FP64 atomic adds (split-K partial products that
+// several workgroups accumulate into one zeroed output; beta is ignored).
+template <int MODE, bool ATOM = false>
 __device__ __forceinline__ void gemm_tile(int M, int N, int k0, int k1, View A, View B, double* C, long crs, long ccs,
                                           double alpha, double beta, int m0, int n0) {
   using T = typename Cfg<MODE>::T;
@@ -149,8 +151,12 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int k0, int k1, View A, 
         if (gm < M && gn < N) {
           double val = alpha * (double)acc[bi][bj][v];
           const gdp cp = Cg + (long)gm * crs + (long)gn * ccs;
-          if (beta != 0.0) val += beta * (*cp);
-          *cp = val;
+          if constexpr (ATOM) {
+            unsafeAtomicAdd((double*)cp, val);
+          } else {
+            if (beta != 0.0) val += beta * (*cp);
+            *cp = val;
+          }
         }
       }
 }

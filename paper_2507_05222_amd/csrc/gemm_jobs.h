@@ -34,7 +34,8 @@ struct GemmJob {
   double alpha, beta;       // C = alpha A B + beta C
   double* part;             // split-K: raw partial tiles ([tile][split][64][64])
   unsigned* ctr;            // split-K: one arrival counter per output tile, zero between launches;
-                            // null: partials only, C is not written (the consumer adds them)
+                            // null: every split adds its product to C with atomic adds (C must
+                            // hold zeros; the order of the additions is not fixed)
 };
 struct GemmBatch {
   int n, maxb;
@@ -65,15 +66,15 @@ __global__ void __launch_bounds__(256) k_gemm_jobs(GemmBatch gb) {
     gemm_tile<MODE>(M, N, 0, K, A, B, j.C + (long)bi * ev(j.sc), ev(j.crs), ev(j.ccs), j.alpha, j.beta, m0, n0);
     return;
   }
-  // Split-K without arrival counters: raw partial tiles only, summed in split order
-  // by the consuming kernel (the kernel boundary orders the accesses).
+  // Split-K without arrival counters: each split adds alpha times its partial
+  // product to C (zeroed by the caller) with FP64 atomic adds.
   constexpr int BKr = Cfg<MODE>::BK;
   if (!j.ctr) {
-    const int tile = blockIdx.y * gridDim.x + blockIdx.x;
     const int kc = ((K + S - 1) / S + BKr - 1) / BKr * BKr;
     const int k0 = min(K, sp * kc), k1 = min(K, k0 + kc);
-    double* P = j.part + ((size_t)tile * S + sp) * TILE * TILE;
-    gemm_tile<MODE>(M, N, k0, k1, A, B, P - ((long)m0 * TILE + n0), TILE, 1, 1.0, 0.0, m0, n0);
+    if (k0 < k1)
+      gemm_tile<MODE, true>(M, N, k0, k1, A, B, j.C + (long)bi * ev(j.sc), ev(j.crs), ev(j.ccs), j.alpha, 0.0, m0,
+                            n0);
     return;
   }
   // Split-K: each split writes its raw partial tile; the last split to arrive

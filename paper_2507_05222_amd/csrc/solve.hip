@@ -48,7 +48,7 @@ struct SGeo {
   double ltol;      // local CG: reduction of the initial local residual
   int maxit;        // CG iterations per local problem
   int lds;          // dynamic LDS budget (bytes) of the gauge-move kernels
-  int mvs, mvtx;    // local matvec: K-splits of its last product and its tiles per row
+  int mvs;          // local matvec: K-splits of its last product (> 1: atomic accumulation)
 };
 
 // workspace layout (doubles)
@@ -121,6 +121,7 @@ __global__ void k_env_init(SBatch sb, SGeo g, SLay l) {
     c.ws[l.Rb + (size_t)g.L * l.envb] = 1.0;
   }
   if (threadIdx.x < S_COUNT) c.ws[l.sc + threadIdx.x] = 0.0;
+  for (int e = threadIdx.x; e < 2 * g.cx * g.cx; e += blockDim.x) c.ws[l.Ap + e] = 0.0;   // accumulated into
   unsigned* ctr = reinterpret_cast<unsigned*>(c.ws + l.ctr);
   for (int i = threadIdx.x; i < SPLIT_CTRS; i += blockDim.x) ctr[i] = 0u;
 }
@@ -168,15 +169,13 @@ __device__ double block_sum(double v, double* red) {
   return t;
 }
 
-// Element e = (a 2 + s) cx + c of the local product M_eff v: the split-K partial
-// tiles of its last GEMM added in split order (or the product itself, unsplit).
-__device__ __forceinline__ double ap_at(const SChain& c, const SGeo& g, const SLay& l, int e) {
-  if (g.mvs <= 1) return c.ws[l.Ap + e];
-  const int row = e / g.cx, col = e % g.cx;
-  const int tile = (row >> 6) * g.mvtx + (col >> 6), within = (row & 63) * 64 + (col & 63);
-  const double* P = c.ws + l.part + (size_t)tile * g.mvs * 4096 + within;
-  double v = 0.0;
-  for (int q = 0; q < g.mvs; ++q) v += P[(size_t)q * 4096];
+// Element e = (a 2 + s) cx + c of the local product M_eff v. With a split last
+// product (g.mvs > 1) the splits accumulate into Ap with atomic adds, so the one
+// reader of each product clears the elements it has read for the next one.
+__device__ __forceinline__ double ap_take(const SChain& c, const SGeo& g, const SLay& l, int e) {
+  const gdp ap = as_global(c.ws + l.Ap);
+  const double v = ap[e];
+  if (g.mvs > 1) ap[e] = 0.0;
   return v;
 }
 
@@ -198,7 +197,7 @@ __global__ void __launch_bounds__(1024) k_cg_init(SBatch sb, SGeo g, SLay l, int
     const int a = e / (2 * cx), cc = e % cx;
     double rv = 0, pv = 0;
     if (a < nl && cc < nr) {
-      rv = beff[e] - ap_at(c, g, l, e);
+      rv = beff[e] - ap_take(c, g, l, e);
       pv = dinv[e] * rv;
       rz += rv * pv; bn += beff[e] * beff[e]; rn += rv * rv;
     }
@@ -259,7 +258,7 @@ __global__ void __launch_bounds__(1024) k_cg_step(SBatch sb, SGeo g, SLay l) {
       const bool in = e < n;
       ok[q] = in && (e / (2 * cx)) < nl && (e % cx) < nr;
       pv[q] = in ? p[e] : 0.0;
-      av[q] = ok[q] ? ap_at(c, g, l, e) : 0.0;
+      av[q] = ok[q] ? ap_take(c, g, l, e) : 0.0;
       xv[q] = ok[q] ? x[e] : 0.0;
       rv[q] = ok[q] ? r[e] : 0.0;
       dv[q] = ok[q] ? dinv[e] : 0.0;
@@ -290,7 +289,7 @@ __global__ void __launch_bounds__(1024) k_cg_step(SBatch sb, SGeo g, SLay l) {
   } else {
     for (int e = tid; e < n; e += blockDim.x) {
       const int a = e / (2 * cx), cc = e % cx;
-      if (a < nl && cc < nr) pAp += p[e] * ap_at(c, g, l, e);
+      if (a < nl && cc < nr) pAp += p[e] * c.ws[l.Ap + e];
     }
     pAp = block_sum(pAp, red);
     alpha = pAp > 0.0 ? rz / pAp : 0.0;
@@ -298,7 +297,7 @@ __global__ void __launch_bounds__(1024) k_cg_step(SBatch sb, SGeo g, SLay l) {
       const int a = e / (2 * cx), cc = e % cx;
       if (a < nl && cc < nr) {
         x[e] += alpha * p[e];
-        const double v = r[e] - alpha * ap_at(c, g, l, e);
+        const double v = r[e] - alpha * ap_take(c, g, l, e);   // second and last read
         r[e] = v;
         rn += v * v;
         rz2 += v * dinv[e] * v;
@@ -621,8 +620,8 @@ struct Solver {
   }
 
   // out = M_eff v at site k (v, out: [a][s][c], row stride cx): T = LM v, then
-  // out = T RA, the last product split over K into raw partial tiles (g.mvs > 1)
-  // that the CG kernels add.
+  // out = T RA, the last product split over K (g.mvs > 1) with the splits added
+  // into the zeroed out by atomic adds; the CG kernels clear out as they read it.
   void matvec(int k, bool v_is_x, int mmode) {
     const int cx = g.cx, W = g.W;
     GemmBatch g1 = batch(1), g3 = batch(1);
@@ -642,7 +641,6 @@ struct Solver {
       d.C = c.ws + l.Ap; d.crs = C_(cx); d.ccs = C_(1);
       d.M = B1(c.xb, k, 2); d.N = B1(c.xb, k + 1); d.K = B1(c.ab, k + 1, cx);
       d.skip = skip;
-      if (g.mvs > 1) { d.part = c.ws + l.part; d.ctr = nullptr; }
     }
     g3.ksplit = g.mvs;
     run_jobs(g1, cx * 2 * W, cx, mmode, s);
@@ -771,14 +769,13 @@ extern "C" int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qt
     }
     S.g = SGeo{L, 0, cx, cb, wcap, W, cx, opts->local_tol, opts->max_local_iters, lds};
     S.g.mvs = ksplit_for(2 * cx, cx, W * cx);
-    S.g.mvtx = cdiv(cx, TILE);
     S.l = lay;
     S.mode = opts->contract_dt;
     S.s = s;
     S.lds = lds;
     S.flags = nullptr;
     hipLaunchKernelGGL(k_transposes, dim3(L, S.sb.n), dim3(256), 0, s, S.sb, S.g, lay);
-    hipLaunchKernelGGL(k_env_init, dim3(S.sb.n), dim3(64), 0, s, S.sb, S.g, lay);
+    hipLaunchKernelGGL(k_env_init, dim3(S.sb.n), dim3(256), 0, s, S.sb, S.g, lay);
     // right-canonical start (bond structure kept), right environments
     for (int k = L - 1; k >= 1; --k) S.rl_move(k);
     for (int k = L - 1; k >= 1; --k) { S.ra_update(k); S.rb_update(k); }
@@ -890,14 +887,13 @@ int fit_sweeps(qtt_ctx* ctx, int n, const qtt_mpo* M, const qtt_mps* x, qtt_mps*
     }
     S.g = SGeo{L, 0, cx, 1, wcap, W, ck, 0.0, 0, lds_of(ctx)};
     S.g.mvs = 1;
-    S.g.mvtx = 1;
     S.l = lay;
     S.mode = mode;
     S.s = s;
     S.lds = lds_of(ctx);
     S.flags = nullptr;
     hipLaunchKernelGGL(k_transposes, dim3(L, S.sb.n), dim3(256), 0, s, S.sb, S.g, lay);
-    hipLaunchKernelGGL(k_env_init, dim3(S.sb.n), dim3(64), 0, s, S.sb, S.g, lay);
+    hipLaunchKernelGGL(k_env_init, dim3(S.sb.n), dim3(256), 0, s, S.sb, S.g, lay);
     for (int k = L - 1; k >= 1; --k) S.ra_update(k, mode);
     for (int sw = 0; sw < sweeps; ++sw) {
       for (int k = 0; k <= L - 2; ++k) {
