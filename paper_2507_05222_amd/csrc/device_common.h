@@ -20,7 +20,7 @@ __host__ __device__ inline size_t align64(size_t x) { return (x + 63) & ~size_t(
 // ---------------------------------------------------------------------------
 // block GEMM tile on MFMA
 //   C(m, n) = alpha * sum_{k0 <= k < k1} A(m, k) B(k, n) + beta * C(m, n)
-//   for m0 <= m < m0 + 64, n0 <= n < n0 + 64 (clipped to M, N).
+//   for m0 <= m < m0 + TS, n0 <= n < n0 + TS (clipped to M, N), TS = 64 or 32.
 // Operands are strided views: A(m, k) = A.p[m*A.rs + k*A.cs]. Values outside the
 // bounds read as zero. MODE 0: FP64 MFMA 16x16x4 (FP64 accumulate); MODE 1: FP32
 // MFMA 16x16x4; MODE 2: BF16 MFMA 16x16x32 (FP32 accumulate).
@@ -53,39 +53,45 @@ __device__ __forceinline__ typename Cfg<MODE>::T to_t(double v) {
 // The K loop keeps the next K-block's global loads in flight (in registers)
 // while the MFMAs of the current block run from LDS: with the small grids of
 // the bond-dimension GEMMs the tile time is dominated by load latency.
+// TS: output tile edge, 64 (each of the four waves owns 32 x 32, four MFMA
+// blocks) or 32 (each wave owns one 16 x 16 block): the small tile puts four
+// times as many workgroups, each with a quarter of the dependent MFMA chain, on
+// a product whose 64 x 64 grid would leave most of the chip idle.
 // ATOM: the tile is added to C with FP64 atomic adds (split-K partial products that
 // several workgroups accumulate into one zeroed output; beta is ignored).
-template <int MODE, bool ATOM = false>
+template <int MODE, bool ATOM = false, int TS = TILE>
 __device__ __forceinline__ void gemm_tile(int M, int N, int k0, int k1, View A, View B, double* C, long crs, long ccs,
                                           double alpha, double beta, int m0, int n0) {
+  static_assert(TS == 64 || TS == 32, "tile edge");
   using T = typename Cfg<MODE>::T;
   using Acc = typename Cfg<MODE>::Acc;
   constexpr int BK = Cfg<MODE>::BK;
   constexpr int PAD = Cfg<MODE>::PAD;
-  constexpr int PER = TILE * BK / 256;     // elements of each operand per thread and K-block
-  __shared__ __attribute__((aligned(16))) T As[TILE][BK + PAD];
-  __shared__ __attribute__((aligned(16))) T Bs[TILE][BK + PAD];
+  constexpr int PER = TS * BK / 256;       // elements of each operand per thread and K-block
+  constexpr int WB = TS / 32;              // 16 x 16 MFMA blocks per wave and dimension
+  __shared__ __attribute__((aligned(16))) T As[TS][BK + PAD];
+  __shared__ __attribute__((aligned(16))) T Bs[TS][BK + PAD];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave >> 1) * (TS / 2), wn = (wave & 1) * (TS / 2);
   const int li = lane & 15, lk = lane >> 4;
   const bool a_kfast = (A.cs == 1), b_nfast = (B.cs == 1);
   const gcdp Ap = as_global(A.p), Bp = as_global(B.p);
   const gdp Cg = as_global(C);
-  Acc acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+  Acc acc[WB][WB];
+  for (int a = 0; a < WB; ++a)
+    for (int b = 0; b < WB; ++b) acc[a][b] = Acc{0, 0, 0, 0};
   T ra[PER], rb[PER];
   auto load = [&](int kb) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = tid + 256 * q;
       int i, kk;
-      if (a_kfast) { i = e / BK; kk = e % BK; } else { i = e % TILE; kk = e / TILE; }
+      if (a_kfast) { i = e / BK; kk = e % BK; } else { i = e % TS; kk = e / TS; }
       const int gm = m0 + i, gk = kb + kk;
       ra[q] = to_t<MODE>((gm < M && gk < k1) ? Ap[(long)gm * A.rs + (long)gk * A.cs] : 0.0);
       int j;
-      if (b_nfast) { j = e % TILE; kk = e / TILE; } else { kk = e % BK; j = e / BK; }
+      if (b_nfast) { j = e % TS; kk = e / TS; } else { kk = e % BK; j = e / BK; }
       const int gn = n0 + j;
       const int gk2 = kb + kk;
       rb[q] = to_t<MODE>((gn < N && gk2 < k1) ? Bp[(long)gk2 * B.rs + (long)gn * B.cs] : 0.0);
@@ -96,10 +102,10 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int k0, int k1, View A, 
     for (int q = 0; q < PER; ++q) {
       const int e = tid + 256 * q;
       int i, kk;
-      if (a_kfast) { i = e / BK; kk = e % BK; } else { i = e % TILE; kk = e / TILE; }
+      if (a_kfast) { i = e / BK; kk = e % BK; } else { i = e % TS; kk = e / TS; }
       As[i][kk] = ra[q];
       int j;
-      if (b_nfast) { j = e % TILE; kk = e / TILE; } else { kk = e % BK; j = e / BK; }
+      if (b_nfast) { j = e % TS; kk = e / TS; } else { kk = e % BK; j = e / BK; }
       Bs[j][kk] = rb[q];
     }
   };
@@ -111,40 +117,44 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int k0, int k1, View A, 
     if constexpr (MODE == 0) {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
-        const double a0 = As[wm + li][kk + lk], a1 = As[wm + 16 + li][kk + lk];
-        const double b0 = Bs[wn + li][kk + lk], b1 = Bs[wn + 16 + li][kk + lk];
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        double av[WB], bv[WB];
+#pragma unroll
+        for (int u = 0; u < WB; ++u) { av[u] = As[wm + 16 * u + li][kk + lk]; bv[u] = Bs[wn + 16 * u + li][kk + lk]; }
+#pragma unroll
+        for (int u = 0; u < WB; ++u)
+#pragma unroll
+          for (int v = 0; v < WB; ++v) acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[v], acc[u][v], 0, 0, 0);
       }
     } else if constexpr (MODE == 1) {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
-        const float a0 = As[wm + li][kk + lk], a1 = As[wm + 16 + li][kk + lk];
-        const float b0 = Bs[wn + li][kk + lk], b1 = Bs[wn + 16 + li][kk + lk];
-        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+        float av[WB], bv[WB];
+#pragma unroll
+        for (int u = 0; u < WB; ++u) { av[u] = As[wm + 16 * u + li][kk + lk]; bv[u] = Bs[wn + 16 * u + li][kk + lk]; }
+#pragma unroll
+        for (int u = 0; u < WB; ++u)
+#pragma unroll
+          for (int v = 0; v < WB; ++v) acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[v], acc[u][v], 0, 0, 0);
       }
     } else {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 32) {
-        const v8bf a0 = *reinterpret_cast<const v8bf*>(&As[wm + li][kk + 8 * lk]);
-        const v8bf a1 = *reinterpret_cast<const v8bf*>(&As[wm + 16 + li][kk + 8 * lk]);
-        const v8bf b0 = *reinterpret_cast<const v8bf*>(&Bs[wn + li][kk + 8 * lk]);
-        const v8bf b1 = *reinterpret_cast<const v8bf*>(&Bs[wn + 16 + li][kk + 8 * lk]);
-        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+        v8bf av[WB], bv[WB];
+#pragma unroll
+        for (int u = 0; u < WB; ++u) {
+          av[u] = *reinterpret_cast<const v8bf*>(&As[wm + 16 * u + li][kk + 8 * lk]);
+          bv[u] = *reinterpret_cast<const v8bf*>(&Bs[wn + 16 * u + li][kk + 8 * lk]);
+        }
+#pragma unroll
+        for (int u = 0; u < WB; ++u)
+#pragma unroll
+          for (int v = 0; v < WB; ++v) acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[u], bv[v], acc[u][v], 0, 0, 0);
       }
     }
     __syncthreads();
   }
-  for (int bi = 0; bi < 2; ++bi)
-    for (int bj = 0; bj < 2; ++bj)
+  for (int bi = 0; bi < WB; ++bi)
+    for (int bj = 0; bj < WB; ++bj)
       for (int v = 0; v < 4; ++v) {
         const int r = (MODE == 0) ? (lk + 4 * v) : (4 * lk + v);
         const int gm = m0 + wm + bi * 16 + r, gn = n0 + wn + bj * 16 + li;

@@ -44,7 +44,7 @@ struct GemmBatch {
   GemmJob j[GB];
 };
 
-template <int MODE>
+template <int MODE, int TS>
 __global__ void __launch_bounds__(256) k_gemm_jobs(GemmBatch gb) {
   const int S = gb.ksplit;
   const int zz = blockIdx.z / S, sp = blockIdx.z % S;
@@ -58,12 +58,13 @@ __global__ void __launch_bounds__(256) k_gemm_jobs(GemmBatch gb) {
     atomicAdd(gb.cnt, 2.0 * M * N * K);
     atomicAdd(gb.cnt + 1, 8.0 * ((double)M * K + (double)K * N + (double)M * N));
   }
-  const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
+  const int m0 = blockIdx.y * TS, n0 = blockIdx.x * TS;
   if (m0 >= M || n0 >= N) return;
   View A{j.A + (long)bi * ev(j.sa), ev(j.ars), ev(j.acs)};
   View B{j.B + (long)bi * ev(j.sb), ev(j.brs), ev(j.bcs)};
   if (S == 1) {
-    gemm_tile<MODE>(M, N, 0, K, A, B, j.C + (long)bi * ev(j.sc), ev(j.crs), ev(j.ccs), j.alpha, j.beta, m0, n0);
+    gemm_tile<MODE, false, TS>(M, N, 0, K, A, B, j.C + (long)bi * ev(j.sc), ev(j.crs), ev(j.ccs), j.alpha, j.beta,
+                               m0, n0);
     return;
   }
   // Split-K without arrival counters: each split adds alpha times its partial
@@ -73,10 +74,11 @@ __global__ void __launch_bounds__(256) k_gemm_jobs(GemmBatch gb) {
     const int kc = ((K + S - 1) / S + BKr - 1) / BKr * BKr;
     const int k0 = min(K, sp * kc), k1 = min(K, k0 + kc);
     if (k0 < k1)
-      gemm_tile<MODE, true>(M, N, k0, k1, A, B, j.C + (long)bi * ev(j.sc), ev(j.crs), ev(j.ccs), j.alpha, 0.0, m0,
-                            n0);
+      gemm_tile<MODE, true, TS>(M, N, k0, k1, A, B, j.C + (long)bi * ev(j.sc), ev(j.crs), ev(j.ccs), j.alpha, 0.0,
+                                m0, n0);
     return;
   }
+  if constexpr (TS != TILE) return;   // ordered finish: 64 x 64 tiles only (the launcher's choice)
   // Split-K: each split writes its raw partial tile; the last split to arrive
   // (arrival counter, no waiting) adds the partials in split order, so the result
   // does not depend on which workgroup finishes last.
@@ -136,16 +138,28 @@ inline int ksplit_for(int maxM, int maxN, int Kmax) {
   return S;
 }
 
+// Launches with fewer than SMALL_GRID workgroups of 64 x 64 tiles use 32 x 32 tiles.
+constexpr long SMALL_GRID = 64;
+
+template <int TS>
+void launch_jobs(const GemmBatch& gb, int maxM, int maxN, int mode, hipStream_t s) {
+  dim3 grid(cdiv(maxN, TS), cdiv(maxM, TS), gb.n * gb.maxb * gb.ksplit);
+  if (mode == 0) hipLaunchKernelGGL((k_gemm_jobs<0, TS>), grid, dim3(256), 0, s, gb);
+  else if (mode == 1) hipLaunchKernelGGL((k_gemm_jobs<1, TS>), grid, dim3(256), 0, s, gb);
+  else hipLaunchKernelGGL((k_gemm_jobs<2, TS>), grid, dim3(256), 0, s, gb);
+}
+
 void run_jobs(const GemmBatch& gb0, int maxM, int maxN, int mode, hipStream_t s) {
   GemmBatch gb = gb0;
   if (gb.ksplit < 1) gb.ksplit = 1;
-  dim3 grid(cdiv(maxN, TILE), cdiv(maxM, TILE), gb.n * gb.maxb * gb.ksplit);
+  bool ordered = false;     // split-K with arrival counters works on 64 x 64 tiles
+  for (int i = 0; i < gb.n; ++i) ordered = ordered || (gb.ksplit > 1 && gb.j[i].ctr);
+  const long wg64 = (long)cdiv(maxN, TILE) * cdiv(maxM, TILE) * gb.n * gb.maxb * gb.ksplit;
   const int kc = (mode == 0) ? KC_JOBS : KC_JOBS_LP;
   qttk::tmark(kc, s);
   gb.cnt = qttk::tcount(kc);   // after the mark: a launch is counted only if it is timed
-  if (mode == 0) hipLaunchKernelGGL(k_gemm_jobs<0>, grid, dim3(256), 0, s, gb);
-  else if (mode == 1) hipLaunchKernelGGL(k_gemm_jobs<1>, grid, dim3(256), 0, s, gb);
-  else hipLaunchKernelGGL(k_gemm_jobs<2>, grid, dim3(256), 0, s, gb);
+  if (!ordered && wg64 < SMALL_GRID) launch_jobs<32>(gb, maxM, maxN, mode, s);
+  else launch_jobs<TILE>(gb, maxM, maxN, mode, s);
   qttk::tmark(kc, s);
 }
 
