@@ -59,7 +59,7 @@ struct FGeo {
 // per-chain workspace: for each term its environments, transposes and scratch
 struct FLay {
   size_t env[MAXT], LA[MAXT], RA[MAXT], Mt[MAXT], Mt2[MAXT], F1[MAXT], F2[MAXT];
-  size_t tmpA, gp, part, ctr, total;
+  size_t tmpA, gp, total;
   static FLay make(int L, int cy, const int* ck, int W, int nt) {
     FLay l;
     size_t o = 0;
@@ -76,8 +76,6 @@ struct FLay {
     }
     l.tmpA = o; o += al(4 * (size_t)cy * cy);
     l.gp = o; o += al(4 * 4 * (size_t)cy * cy);
-    l.part = o; o += al((size_t)SPLIT_SLOTS * TILE * TILE);
-    l.ctr = o; o += al(SPLIT_CTRS / 2);
     l.total = o;
     return l;
   }
@@ -106,8 +104,6 @@ __global__ void k_fit_transposes(FBatch fb, FGeo g, FLay l) {
 
 __global__ void k_fit_env_init(FBatch fb, FGeo g, FLay l) {
   if (blockIdx.x >= fb.n) return;
-  unsigned* ctr = reinterpret_cast<unsigned*>(fb.c[blockIdx.x].ws + l.ctr);
-  for (int i = threadIdx.x; i < SPLIT_CTRS; i += blockDim.x) ctr[i] = 0u;
   if (threadIdx.x != 0) return;
   for (int t = 0; t < fb.nt; ++t) {
     fb.c[blockIdx.x].ws[l.LA[t]] = 1.0;
@@ -276,26 +272,31 @@ struct Fitter {
     run(b, g.cy, 2 * g.W, maxck, mode);
   }
 
-  // Y_k = sum_t c_t F2_t . RA^t_{k+1}  (terms accumulate one launch after the other)
+  // Y_k = sum_t c_t F2_t . RA^t_{k+1}: Y_k is zeroed, then every (chain, term) product,
+  // split over K, adds into it with atomic adds.
   void project(int k) {
     steps12(k);
+    ZeroList z{fb.n, (long)g.cy * 2 * g.cy, {}};
+    for (int i = 0; i < fb.n; ++i) z.p[i] = fb.c[i].y + (size_t)k * g.cy * 2 * g.cy;
+    zero_list(z, s);
+    std::vector<GemmJob> d;
+    int ks = 1;
     for (int t = 0; t < fb.nt; ++t) {
-      std::vector<GemmJob> d;
+      ks = std::max(ks, ksplit_for(2 * g.cy, g.cy, g.wcap[t] * g.ck[t]));
       for (int i = 0; i < fb.n; ++i) {
         const FChain& c = fb.c[i];
         const FTerm& tm = c.t[t];
         const int ck = g.ck[t];
-        GemmJob j; one(j);     // Y[(a,s')][c] (+)= coef F2[(a,s')][(b',c')] RA[c][(b',c')]
+        GemmJob j; one(j);     // Y[(a,s')][c] += coef F2[(a,s')][(b',c')] RA[c][(b',c')]
         j.A = c.ws + l.F2[t]; j.ars = B1(tm.ab, k + 1, ck); j.acs = C_(1);
         j.B = c.ws + l.RA[t] + (size_t)(k + 1) * l.env[t]; j.brs = C_(1); j.bcs = B1(tm.ab, k + 1, ck);
         j.C = c.y + (size_t)k * g.cy * 2 * g.cy; j.crs = C_(g.cy); j.ccs = C_(1);
         j.M = B1(c.yb, k, 2); j.N = B1(c.yb, k + 1); j.K = B1(tm.ab, k + 1, ck);
-        j.alpha = tm.coef; j.beta = (t == 0) ? 0.0 : 1.0;
-        j.part = c.ws + l.part; j.ctr = reinterpret_cast<unsigned*>(c.ws + l.ctr);
+        j.alpha = tm.coef;
         d.push_back(j);
       }
-      run(d, 1, 2 * g.cy, g.cy, mode, ksplit_for(2 * g.cy, g.cy, g.wcap[t] * g.ck[t]));
     }
+    run(d, 1, 2 * g.cy, g.cy, mode, std::max(ks, 2));
   }
 
   // LA^t_{k+1}[p][(b', q)] = sum_{(a, s')} Y_k[(a, s')][p] F2_t[(a, s')][(b', q)]

@@ -31,12 +31,11 @@ struct GemmJob {
   IE M, N, K;
   IE nb, sa, sb, sc;        // batch count and batch strides
   const double* skip;       // if non-null and *skip != 0, the job is skipped
-  double alpha, beta;       // C = alpha A B + beta C
-  double* part;             // split-K: raw partial tiles ([tile][split][64][64])
-  unsigned* ctr;            // split-K: one arrival counter per output tile, zero between launches;
-                            // null: every split adds its product to C with atomic adds (C must
-                            // hold zeros; the order of the additions is not fixed)
+  double alpha, beta;       // C = alpha A B + beta C; split over K: C += alpha A B
 };
+// Split over K (ksplit > 1): every split adds alpha times its partial product to C
+// with FP64 atomic adds, so C must hold zeros (or the sum so far) beforehand and
+// the order of the additions is not fixed.
 struct GemmBatch {
   int n, maxb;
   int ksplit;               // K-splits per output tile (1: none; jobs must then have nb == 1)
@@ -67,75 +66,37 @@ __global__ void __launch_bounds__(256) k_gemm_jobs(GemmBatch gb) {
                                m0, n0);
     return;
   }
-  // Split-K without arrival counters: each split adds alpha times its partial
-  // product to C (zeroed by the caller) with FP64 atomic adds.
-  constexpr int BKr = Cfg<MODE>::BK;
-  if (!j.ctr) {
-    const int kc = ((K + S - 1) / S + BKr - 1) / BKr * BKr;
-    const int k0 = min(K, sp * kc), k1 = min(K, k0 + kc);
-    if (k0 < k1)
-      gemm_tile<MODE, true, TS>(M, N, k0, k1, A, B, j.C + (long)bi * ev(j.sc), ev(j.crs), ev(j.ccs), j.alpha, 0.0,
-                                m0, n0);
-    return;
-  }
-  if constexpr (TS != TILE) return;   // ordered finish: 64 x 64 tiles only (the launcher's choice)
-  // Split-K: each split writes its raw partial tile; the last split to arrive
-  // (arrival counter, no waiting) adds the partials in split order, so the result
-  // does not depend on which workgroup finishes last.
-  constexpr int BK = Cfg<MODE>::BK;
-  const int tile = blockIdx.y * gridDim.x + blockIdx.x;
-  const int kc = ((K + S - 1) / S + BK - 1) / BK * BK;
+  const int kc = ((K + S - 1) / S + Cfg<MODE>::BK - 1) / Cfg<MODE>::BK * Cfg<MODE>::BK;
   const int k0 = min(K, sp * kc), k1 = min(K, k0 + kc);
-  double* P = j.part + (size_t)tile * S * TILE * TILE;
-  gemm_tile<MODE>(M, N, k0, k1, A, B, P + (size_t)sp * TILE * TILE - ((long)m0 * TILE + n0), TILE, 1, 1.0, 0.0, m0, n0);
-  __threadfence();
-  __syncthreads();
-  __shared__ int last;
-  if (threadIdx.x == 0) last = (atomicAdd(j.ctr + tile, 1u) == (unsigned)(S - 1));
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  const long crs = ev(j.crs), ccs = ev(j.ccs);
-  const gdp C = as_global(j.C);
-  const gcdp Pg = as_global((const double*)P);
-  // four elements per thread and pass, all partial loads issued before any add
-  for (int e0 = threadIdx.x; e0 < TILE * TILE; e0 += 4 * 256) {
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    double pv[4][8];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) pv[u][q] = (q < S) ? Pg[(size_t)q * TILE * TILE + e0 + u * 256] : 0.0;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) v[u] += pv[u][q];
-      const int e = e0 + u * 256;
-      const int gm = m0 + e / TILE, gn = n0 + e % TILE;
-      if (gm < M && gn < N) {
-        const gdp cp = C + (long)gm * crs + (long)gn * ccs;
-        double r = v[u] * j.alpha;
-        if (j.beta != 0.0) r += j.beta * (*cp);
-        *cp = r;
-      }
-    }
-  }
-  if (threadIdx.x == 0) j.ctr[tile] = 0u;
+  if (k0 < k1)
+    gemm_tile<MODE, true, TS>(M, N, k0, k1, A, B, j.C + (long)bi * ev(j.sc), ev(j.crs), ev(j.ccs), j.alpha, 0.0, m0,
+                              n0);
+}
+
+// Zero fill of up to QTT_BMAX buffers of len doubles (outputs of split products).
+struct ZeroList {
+  int n;
+  long len;
+  double* p[QTT_BMAX];
+};
+__global__ void k_zero_list(ZeroList z) {
+  if ((int)blockIdx.y >= z.n) return;
+  const gdp p = as_global(z.p[blockIdx.y]);
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < z.len; e += (long)gridDim.x * blockDim.x) p[e] = 0.0;
+}
+void zero_list(const ZeroList& z, hipStream_t s) {
+  if (z.n > 0 && z.len > 0)
+    hipLaunchKernelGGL(k_zero_list, dim3((unsigned)std::min<long>(16, (z.len + 1023) / 1024), z.n), dim3(256), 0, s, z);
 }
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-constexpr int SPLIT_SLOTS = 32;   // partial tiles per chain workspace (tiles * splits)
-constexpr int SPLIT_CTRS = 128;   // arrival counters per chain workspace
 // K-splits for a GEMM with few output tiles and a long K: aim at ~24 workgroups
-// per job, at least 64 of K per split.
+// of 64 x 64 tiles per job, at least 64 of K per split.
 inline int ksplit_for(int maxM, int maxN, int Kmax) {
   const int tiles = cdiv(maxM, TILE) * cdiv(maxN, TILE);
-  int S = std::min(24 / std::max(tiles, 1), Kmax / 64);
-  S = std::max(1, std::min(S, 8));
-  while (S > 1 && tiles * S > SPLIT_SLOTS) --S;
-  if (tiles > SPLIT_CTRS) S = 1;
-  return S;
+  const int S = std::min(24 / std::max(tiles, 1), Kmax / 64);
+  return std::max(1, std::min(S, 8));
 }
 
 // Launches with fewer than SMALL_GRID workgroups of 64 x 64 tiles use 32 x 32 tiles.
@@ -152,13 +113,11 @@ void launch_jobs(const GemmBatch& gb, int maxM, int maxN, int mode, hipStream_t 
 void run_jobs(const GemmBatch& gb0, int maxM, int maxN, int mode, hipStream_t s) {
   GemmBatch gb = gb0;
   if (gb.ksplit < 1) gb.ksplit = 1;
-  bool ordered = false;     // split-K with arrival counters works on 64 x 64 tiles
-  for (int i = 0; i < gb.n; ++i) ordered = ordered || (gb.ksplit > 1 && gb.j[i].ctr);
   const long wg64 = (long)cdiv(maxN, TILE) * cdiv(maxM, TILE) * gb.n * gb.maxb * gb.ksplit;
   const int kc = (mode == 0) ? KC_JOBS : KC_JOBS_LP;
   qttk::tmark(kc, s);
   gb.cnt = qttk::tcount(kc);   // after the mark: a launch is counted only if it is timed
-  if (!ordered && wg64 < SMALL_GRID) launch_jobs<32>(gb, maxM, maxN, mode, s);
+  if (wg64 < SMALL_GRID) launch_jobs<32>(gb, maxM, maxN, mode, s);
   else launch_jobs<TILE>(gb, maxM, maxN, mode, s);
   qttk::tmark(kc, s);
 }

@@ -53,7 +53,7 @@ struct SGeo {
 
 // workspace layout (doubles)
 struct SLay {
-  size_t LA, RA, Lb, Rb, F1, F2, F3, Mt, Mt2, beff, r, p, Ap, dinv, sc, tmpA, gp, part, ctr, LM, total;
+  size_t LA, RA, Lb, Rb, F1, F2, F3, Mt, Mt2, beff, r, p, Ap, dinv, sc, tmpA, gp, LM, total;
   size_t env, envb;
   static SLay make(int L, int cx, int ck, int cb, int W) {
     SLay l;
@@ -79,8 +79,6 @@ struct SLay {
     l.sc = o; o += 64;
     l.tmpA = o; o += al(4 * (size_t)cx * cx);
     l.gp = o; o += al(4 * 4 * (size_t)cx * cx);
-    l.part = o; o += al((size_t)SPLIT_SLOTS * TILE * TILE);
-    l.ctr = o; o += al(SPLIT_CTRS / 2);
     l.LM = o; o += al((size_t)cx * 2 * W * 2 * cx);
     l.total = o;
     return l;
@@ -122,8 +120,6 @@ __global__ void k_env_init(SBatch sb, SGeo g, SLay l) {
   }
   if (threadIdx.x < S_COUNT) c.ws[l.sc + threadIdx.x] = 0.0;
   for (int e = threadIdx.x; e < 2 * g.cx * g.cx; e += blockDim.x) c.ws[l.Ap + e] = 0.0;   // accumulated into
-  unsigned* ctr = reinterpret_cast<unsigned*>(c.ws + l.ctr);
-  for (int i = threadIdx.x; i < SPLIT_CTRS; i += blockDim.x) ctr[i] = 0u;
 }
 
 // start of a sweep: clear the maximum of the projected residuals
@@ -521,6 +517,9 @@ struct Solver {
   void project(int k, int mmode) {
     const int cx = g.cx, ck = g.ck, W = g.W;
     la_steps12(k, mmode);
+    ZeroList z{sb.n, (long)cx * 2 * cx, {}};
+    for (int i = 0; i < sb.n; ++i) z.p[i] = sb.c[i].x + (size_t)k * cx * 2 * cx;
+    zero_list(z, s);                   // the split product below accumulates into X_k
     GemmBatch g3 = batch(1);
     for (int i = 0; i < sb.n; ++i) {
       const SChain& c = sb.c[i];
@@ -529,7 +528,6 @@ struct Solver {
       d.B = c.ws + l.RA + (size_t)(k + 1) * l.env; d.brs = C_(1); d.bcs = B1(c.ab, k + 1, ck);
       d.C = c.x + (size_t)k * cx * 2 * cx; d.crs = C_(cx); d.ccs = C_(1);
       d.M = B1(c.xb, k, 2); d.N = B1(c.xb, k + 1); d.K = B1(c.ab, k + 1, ck);
-      d.part = c.ws + l.part; d.ctr = reinterpret_cast<unsigned*>(c.ws + l.ctr);
     }
     g3.ksplit = ksplit_for(2 * cx, cx, W * ck);
     run_jobs(g3, 2 * cx, cx, mmode, s);
