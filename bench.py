@@ -98,8 +98,10 @@ def dense(Q, F, m, n):
 def sweep(args):
     """Isolated kernel sweep: random MPS (L = 24, cores N(0, 1/chi)) times random MPO
     (bond w, entries N(0, 1)), zip-up apply plus rounding to chi, `trials` chains per
-    call. Reports the site-contraction kernels (k_zip_t1, k_zip_t2) in TFLOP/s from the
-    library's work counters and HIP-event brackets, and the whole apply time."""
+    call. Reports the site contractions in TFLOP/s from the library's work counters and
+    HIP-event brackets, and the whole apply time. In FP64 at slot capacity 64 or 128 both
+    contractions of a site run in one kernel (k_zip_fused, reported under carry_x_core,
+    "fused": true); otherwise k_zip_t1 (carry_x_core) and k_zip_t2 (x_mpo_core)."""
     import torch
     from paper_2507_05222_amd import qtt as Q
     from qtt_inputs import random_mps_cores, random_mpo_cores
@@ -131,6 +133,7 @@ def sweep(args):
                 tot_ms = (a["launches"] * a["avg_us"] + b["launches"] * b["avg_us"]) * 1e-3
                 tf = (a["gflop"] + b["gflop"]) / max(tot_ms, 1e-9)
                 rec["contraction"] = {"tflops": round(tf, 3), "frac_of_peak": round(tf / PEAKS[dt], 5)}
+                rec["fused"] = b["launches"] == 0 and a["launches"] > 0
                 print(json.dumps(rec), flush=True)
             del Ms, ys
             torch.cuda.empty_cache()

@@ -171,8 +171,7 @@ void zipup(const Batch& b, Geo g, const WsLayout& wl, hipStream_t s) {
   qttk::mpo_transpose(b, g, s);
   for (int k = 0; k < g.L; ++k) {
     g.k = k;
-    qttk::zip_t1(b, g, s);
-    qttk::zip_t2(b, g, s);
+    qttk::zip_contract(b, g, s);
     if (k < g.L - 1) {
       qttk::zip_gram(b, g, s);
       qttk::zip_factor(b, g, s);

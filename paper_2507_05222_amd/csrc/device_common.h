@@ -208,6 +208,40 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
+// Value of v in lane l (l uniform over the wavefront).
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// N independent wave sums at once: every DPP step is applied to all N values
+// before the next, so the N dependency chains interleave instead of running
+// one after the other.
+template <int N>
+__device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_move<0x111>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_move<0x112>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_move<0x114>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_move<0x118>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_move<0x142>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] += dpp_move<0x143>(v[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v[q]);
+    const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), 63);
+    const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+    v[q] = __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+  }
+}
+
 // Maximum over the 64 lanes of a wavefront (same DPP pattern as wave_sum).
 __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_move<0x111>(v));
@@ -227,16 +261,100 @@ __device__ __forceinline__ double wave_max(double v) {
 // bond carries hold rounding noise that shrinks geometrically along a sweep, and
 // 1/|v|^2 of such a column would overflow.
 constexpr double HH_TINY = 1e-290;
+// Columns whose largest entry lies outside (HH_SMALL, HH_BIG) are rescaled before
+// |x|^2 is formed (its terms could underflow or overflow); others are used as they are.
+constexpr double HH_SMALL = 1e-100, HH_BIG = 1e100;
+
+// One round of the parallel cyclic ordering with the columns in registers: each
+// wavefront takes P pairs at a time, loads their 2P columns (m <= 64 T) in one go,
+// reduces the P inner products together and rotates. Per pair the arithmetic and
+// the order of every sum are those of the one-pair loop in jacobi_cols.
+template <int T, int P>
+__device__ __forceinline__ void jacobi_round_regs(double* X, int m, int ldx, int n, double* V, int ldv, int ne, int r,
+                                                  double* nrm, double tiny2, double tol, int* flag, int* nrot) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int base = wave * P; base < ne / 2; base += nw * P) {
+    int pp[P], qq[P];
+    bool act[P];
+    double a[P], b[P], c[P];
+    double xp[P][T], xq[P][T];
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      const int pi = base + u;
+      int p = n, q = n;
+      if (pi < ne / 2) {
+        if (pi == 0) { p = ne - 1; q = r; }
+        else { p = (r + pi) % (ne - 1); q = (r - pi + ne - 1) % (ne - 1); }
+      }
+      // p, q are uniform over the wavefront: scalar registers
+      p = __builtin_amdgcn_readfirstlane(p);
+      q = __builtin_amdgcn_readfirstlane(q);
+      act[u] = p < n && q < n;
+      a[u] = act[u] ? nrm[p] : 0.0;
+      b[u] = act[u] ? nrm[q] : 0.0;
+      act[u] = act[u] && (a[u] > tiny2) && (b[u] > tiny2);
+      pp[u] = p; qq[u] = q;
+    }
+#pragma unroll
+    for (int u = 0; u < P; ++u)
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int i = lane + 64 * t;
+        const bool ok = act[u] && i < m;
+        xp[u][t] = ok ? X[(long)pp[u] * ldx + i] : 0.0;
+        xq[u][t] = ok ? X[(long)qq[u] * ldx + i] : 0.0;
+      }
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      c[u] = 0.0;
+#pragma unroll
+      for (int t = 0; t < T; ++t) c[u] += xp[u][t] * xq[u][t];
+    }
+    wave_sum_n<P>(c);
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      if (!act[u] || fabs(c[u]) <= tol * sqrt(a[u]) * sqrt(b[u])) continue;
+      const double zeta = (b[u] - a[u]) / (2.0 * c[u]);
+      const double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+      const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int i = lane + 64 * t;
+        if (i < m) {
+          X[(long)pp[u] * ldx + i] = cs * xp[u][t] - sn * xq[u][t];
+          X[(long)qq[u] * ldx + i] = sn * xp[u][t] + cs * xq[u][t];
+        }
+      }
+      if (V) {
+        double* vp = V + (long)pp[u] * ldv;
+        double* vq = V + (long)qq[u] * ldv;
+        for (int i = lane; i < n; i += 64) {
+          const double x = vp[i], w = vq[i];
+          vp[i] = cs * x - sn * w;
+          vq[i] = sn * x + cs * w;
+        }
+      }
+      if (lane == 0) {
+        nrm[pp[u]] = a[u] - tt * c[u];
+        nrm[qq[u]] = b[u] + tt * c[u];
+        *flag = 1;
+        atomicAdd(nrot, 1);
+      }
+    }
+  }
+}
 
 // One-sided Jacobi (Hestenes 1958) on the n columns of X (m rows; column j at
 // X + j*ldx), n <= 512. Rotations are accumulated into V (n x n, column j at
 // V + j*ldv) when V is not null. Parallel cyclic (round-robin) ordering: each round
-// rotates n/2 disjoint column pairs, one pair per wavefront at a time. Column
-// norms are kept in LDS and updated with the rotation (a' = a - t g, b' = b + t g),
-// recomputed exactly at the start of every sweep, so a pair costs one wavefront
-// reduction (its inner product g). Stops after a sweep without rotations
+// rotates n/2 disjoint column pairs. Column norms are kept in LDS and updated with
+// the rotation (a' = a - t g, b' = b + t g), recomputed exactly at the start of
+// every sweep, so a pair costs one wavefront reduction (its inner product g). For
+// m <= 256 the pairs of a wavefront are taken four at a time with their columns in
+// registers (jacobi_round_regs), which hides the load latency of a matrix that
+// lives in global memory. Stops after a sweep without rotations
 // (|x_p.x_q| <= tol |x_p| |x_q|).
-__device__ void jacobi_cols(double* X, int m, int ldx, int n, double* V, int ldv, int* flag,
+__device__ __forceinline__ void jacobi_cols(double* X, int m, int ldx, int n, double* V, int ldv, int* flag,
                             double* cnt = nullptr) {
   __shared__ double nrm[512];
   __shared__ double fro2_s[16];
@@ -265,41 +383,47 @@ __device__ void jacobi_cols(double* X, int m, int ldx, int n, double* V, int ldv
     // their inner products are noise, so they count as converged
     const double tiny2 = 1e-30 * fro2 + 1e-300;
     for (int r = 0; r < ne - 1; ++r) {
-      for (int pi = wave; pi < ne / 2; pi += nw) {
-        int p, q;
-        if (pi == 0) { p = ne - 1; q = r; }
-        else { p = (r + pi) % (ne - 1); q = (r - pi + ne - 1) % (ne - 1); }
-        if (p >= n || q >= n) continue;
-        const double a = nrm[p], b = nrm[q];
-        if (!(a > tiny2) || !(b > tiny2)) continue;
-        double* xp = X + (long)p * ldx;
-        double* xq = X + (long)q * ldx;
-        double c = 0;
-        for (int i = lane; i < m; i += 64) c += xp[i] * xq[i];
-        c = wave_sum(c);
-        if (fabs(c) <= tol * sqrt(a) * sqrt(b)) continue;
-        const double zeta = (b - a) / (2.0 * c);
-        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-        for (int i = lane; i < m; i += 64) {
-          const double u = xp[i], w = xq[i];
-          xp[i] = cs * u - sn * w;
-          xq[i] = sn * u + cs * w;
-        }
-        if (V) {
-          double* vp = V + (long)p * ldv;
-          double* vq = V + (long)q * ldv;
-          for (int i = lane; i < n; i += 64) {
-            const double u = vp[i], w = vq[i];
-            vp[i] = cs * u - sn * w;
-            vq[i] = sn * u + cs * w;
+      if (m <= 128) {
+        jacobi_round_regs<2, 4>(X, m, ldx, n, V, ldv, ne, r, nrm, tiny2, tol, flag, &nrot);
+      } else if (m <= 256) {
+        jacobi_round_regs<4, 2>(X, m, ldx, n, V, ldv, ne, r, nrm, tiny2, tol, flag, &nrot);
+      } else {
+        for (int pi = wave; pi < ne / 2; pi += nw) {
+          int p, q;
+          if (pi == 0) { p = ne - 1; q = r; }
+          else { p = (r + pi) % (ne - 1); q = (r - pi + ne - 1) % (ne - 1); }
+          if (p >= n || q >= n) continue;
+          const double a = nrm[p], b = nrm[q];
+          if (!(a > tiny2) || !(b > tiny2)) continue;
+          double* xp = X + (long)p * ldx;
+          double* xq = X + (long)q * ldx;
+          double c = 0;
+          for (int i = lane; i < m; i += 64) c += xp[i] * xq[i];
+          c = wave_sum(c);
+          if (fabs(c) <= tol * sqrt(a) * sqrt(b)) continue;
+          const double zeta = (b - a) / (2.0 * c);
+          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          for (int i = lane; i < m; i += 64) {
+            const double u = xp[i], w = xq[i];
+            xp[i] = cs * u - sn * w;
+            xq[i] = sn * u + cs * w;
           }
-        }
-        if (lane == 0) {
-          nrm[p] = a - t * c;
-          nrm[q] = b + t * c;
-          *flag = 1;
-          atomicAdd(&nrot, 1);
+          if (V) {
+            double* vp = V + (long)p * ldv;
+            double* vq = V + (long)q * ldv;
+            for (int i = lane; i < n; i += 64) {
+              const double u = vp[i], w = vq[i];
+              vp[i] = cs * u - sn * w;
+              vq[i] = sn * u + cs * w;
+            }
+          }
+          if (lane == 0) {
+            nrm[p] = a - t * c;
+            nrm[q] = b + t * c;
+            *flag = 1;
+            atomicAdd(&nrot, 1);
+          }
         }
       }
       __syncthreads();
@@ -436,26 +560,45 @@ __device__ void qr_regs(double* X, int m, int n, double* rdiag, double* tau, dou
         for (int sl = 0; sl < CPW; ++sl)
           if (sl == sj) col[i] = reg[sl][i];
       }
-      // reflector of the column scaled by its largest entry (scale-invariant, no
-      // underflow of |v|^2): H = I - tau v v^T with v = x / mx, v_j = x_j / mx - alpha
-      double mx = 0.0;
+      // reflector H = I - tau v v^T, v = x sc with v_j = x_j sc - alpha. The largest
+      // entry mx and |x|^2 reduce together; sc = 1 unless mx is so small that |x|^2
+      // could underflow, where the column is rescaled by 1 / mx (scale-invariant).
+      double mx = 0.0, ss = 0.0, xs = 0.0;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
         const int row = lane + 64 * i;
-        if (row >= j && row < m) mx = fmax(mx, fabs(col[i]));
+        if (row >= j && row < m) { mx = fmax(mx, fabs(col[i])); ss += col[i] * col[i]; }
+        if (i == (j >> 6)) xs = col[i];
       }
-      mx = wave_max(mx);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        double t0, t1;
+        switch (q) {
+          case 0: t0 = dpp_move<0x111>(mx); t1 = dpp_move<0x111>(ss); break;
+          case 1: t0 = dpp_move<0x112>(mx); t1 = dpp_move<0x112>(ss); break;
+          case 2: t0 = dpp_move<0x114>(mx); t1 = dpp_move<0x114>(ss); break;
+          case 3: t0 = dpp_move<0x118>(mx); t1 = dpp_move<0x118>(ss); break;
+          case 4: t0 = dpp_move<0x142>(mx); t1 = dpp_move<0x142>(ss); break;
+          default: t0 = dpp_move<0x143>(mx); t1 = dpp_move<0x143>(ss); break;
+        }
+        mx = fmax(mx, t0);
+        ss += t1;
+      }
+      mx = lane_value(mx, 63);
+      ss = lane_value(ss, 63);
       const bool live = mx > HH_TINY;
-      const double sc = live ? 1.0 / mx : 0.0;
-      double ss = 0.0, x0l = 0.0;
+      const bool rescale = live && !(mx > HH_SMALL && mx < HH_BIG);
+      const double sc = !live ? 0.0 : (rescale ? 1.0 / mx : 1.0);
+      if (rescale) {
+        ss = 0.0;
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int row = lane + 64 * i;
-        if (row >= j && row < m) ss += (col[i] * sc) * (col[i] * sc);
-        if (row == j) x0l = col[i] * sc;
+        for (int i = 0; i < RPL; ++i) {
+          const int row = lane + 64 * i;
+          if (row >= j && row < m) ss += (col[i] * sc) * (col[i] * sc);
+        }
+        ss = wave_sum(ss);
       }
-      ss = wave_sum(ss);
-      const double x0 = wave_sum(x0l);        // exactly one lane contributes
+      const double x0 = lane_value(xs, j & 63) * sc;
       double alpha = 0.0, v0 = 0.0, tj = 0.0;
       if (live) {
         const double nrm = sqrt(ss);
@@ -473,7 +616,7 @@ __device__ void qr_regs(double* X, int m, int n, double* rdiag, double* tau, dou
           X[(long)j * m + row] = (row < j) ? col[i] : v;
         }
       }
-      if (lane == 0) { tau[j] = tj; rdiag[j] = alpha * mx; }
+      if (lane == 0) { tau[j] = tj; rdiag[j] = rescale ? alpha * mx : alpha; }
     }
     __syncthreads();
     const double tj = tau[j];
@@ -484,6 +627,8 @@ __device__ void qr_regs(double* X, int m, int n, double* rdiag, double* tau, dou
         const int row = lane + 64 * i;
         vr[i] = (row < m) ? vb[row] : 0.0;
       }
+      // only the columns still to be reduced (c > j): the wave reductions are bound
+      // by VALU issue, so skipping finished columns beats reducing all of them at once
 #pragma unroll
       for (int sl = 0; sl < CPW; ++sl) {
         const int c = sl * 16 + wave;

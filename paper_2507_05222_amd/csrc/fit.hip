@@ -149,6 +149,7 @@ __global__ void k_fit_random(FBatch fb, FGeo g) {
 }
 
 // Householder QR (left-to-right move, bond kept) and LQ (right-to-left move) of core k of y
+template <int RPL, int CPW>
 __global__ void __launch_bounds__(1024) k_fit_lr_qr(FBatch fb, FGeo g, FLay l) {
   extern __shared__ double smem[];
   __shared__ double rdiag[512], tau[512], vbuf[1024];
@@ -157,7 +158,7 @@ __global__ void __launch_bounds__(1024) k_fit_lr_qr(FBatch fb, FGeo g, FLay l) {
   const int k = g.k, cap = g.cy;
   const int m = 2 * c.yb[k], n = c.yb[k + 1];
   const int r = m < n ? m : n;
-  const bool fast = (m <= 256 && n <= 128);
+  const bool fast = RPL > 0 && m <= 64 * RPL && n <= 16 * CPW;
   const size_t need = ((size_t)m * n + (fast ? 0 : (size_t)m * r)) * sizeof(double);
   double* X = (need <= (size_t)g.lds) ? smem : (c.ws + l.gp);
   double* Yk = c.y + (long)k * sl2(cap);
@@ -170,8 +171,7 @@ __global__ void __launch_bounds__(1024) k_fit_lr_qr(FBatch fb, FGeo g, FLay l) {
   if (fast) {
     for (int e = threadIdx.x; e < S; e += blockDim.x) Yk[e] = 0.0;
     auto qs = [&](int i, int j, double v) { Yk[(long)i * cap + j] = v; };
-    if (m <= 128 && n <= 64) qr_regs<2, 4>(X, m, n, rdiag, tau, vbuf, qs);
-    else qr_regs<4, 8>(X, m, n, rdiag, tau, vbuf, qs);
+    if constexpr (RPL > 0) qr_regs<RPL, CPW>(X, m, n, rdiag, tau, vbuf, qs);
   } else {
     double* Q = X + (size_t)m * n;
     householder(X, m, n, rdiag, tau);
@@ -184,6 +184,7 @@ __global__ void __launch_bounds__(1024) k_fit_lr_qr(FBatch fb, FGeo g, FLay l) {
   if (threadIdx.x == 0) c.yb[k + 1] = r;
 }
 
+template <int RPL, int CPW>
 __global__ void __launch_bounds__(1024) k_fit_rl_lq(FBatch fb, FGeo g, FLay l) {
   extern __shared__ double smem[];
   __shared__ double rdiag[512], tau[512], vbuf[1024];
@@ -192,7 +193,7 @@ __global__ void __launch_bounds__(1024) k_fit_rl_lq(FBatch fb, FGeo g, FLay l) {
   const int k = g.k, cap = g.cy;
   const int nb = c.yb[k], mb = c.yb[k + 1];
   const int m = 2 * mb, n = nb, r = m < n ? m : n;
-  const bool fast = (m <= 256 && n <= 128);
+  const bool fast = RPL > 0 && m <= 64 * RPL && n <= 16 * CPW;
   const size_t need = ((size_t)m * n + (fast ? 0 : (size_t)m * r)) * sizeof(double);
   double* X = (need <= (size_t)g.lds) ? smem : (c.ws + l.gp);
   double* Yk = c.y + (long)k * sl2(cap);
@@ -205,8 +206,7 @@ __global__ void __launch_bounds__(1024) k_fit_rl_lq(FBatch fb, FGeo g, FLay l) {
   if (fast) {
     for (int e = threadIdx.x; e < S; e += blockDim.x) Yk[e] = 0.0;
     auto qs = [&](int rho, int j, double v) { Yk[(long)j * 2 * cap + (rho / mb) * cap + rho % mb] = v; };
-    if (m <= 128 && n <= 64) qr_regs<2, 4>(X, m, n, rdiag, tau, vbuf, qs);
-    else qr_regs<4, 8>(X, m, n, rdiag, tau, vbuf, qs);
+    if constexpr (RPL > 0) qr_regs<RPL, CPW>(X, m, n, rdiag, tau, vbuf, qs);
   } else {
     double* Q = X + (size_t)m * n;
     householder(X, m, n, rdiag, tau);
@@ -360,14 +360,18 @@ struct Fitter {
     FGeo gg = g;
     gg.k = k;
     qttk::tmark(KC_LR_QR, s);
-    hipLaunchKernelGGL(k_fit_lr_qr, dim3(fb.n), dim3(1024), g.lds, s, fb, gg, l);
+    if (g.cy <= 64) hipLaunchKernelGGL((k_fit_lr_qr<2, 4>), dim3(fb.n), dim3(1024), g.lds, s, fb, gg, l);
+    else if (g.cy <= 128) hipLaunchKernelGGL((k_fit_lr_qr<4, 8>), dim3(fb.n), dim3(1024), g.lds, s, fb, gg, l);
+    else hipLaunchKernelGGL((k_fit_lr_qr<0, 0>), dim3(fb.n), dim3(1024), g.lds, s, fb, gg, l);
     qttk::tmark(KC_LR_QR, s);
   }
   void lq(int k) {
     FGeo gg = g;
     gg.k = k;
     qttk::tmark(KC_LR_QR, s);
-    hipLaunchKernelGGL(k_fit_rl_lq, dim3(fb.n), dim3(1024), g.lds, s, fb, gg, l);
+    if (g.cy <= 64) hipLaunchKernelGGL((k_fit_rl_lq<2, 4>), dim3(fb.n), dim3(1024), g.lds, s, fb, gg, l);
+    else if (g.cy <= 128) hipLaunchKernelGGL((k_fit_rl_lq<4, 8>), dim3(fb.n), dim3(1024), g.lds, s, fb, gg, l);
+    else hipLaunchKernelGGL((k_fit_rl_lq<0, 0>), dim3(fb.n), dim3(1024), g.lds, s, fb, gg, l);
     qttk::tmark(KC_LR_QR, s);
   }
 };
@@ -376,8 +380,11 @@ struct Fitter {
 
 namespace qtt_solver_detail {
 hipError_t fit_init(int lds) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_fit_lr_qr, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_fit_rl_lq, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  const void* fns[] = {(const void*)k_fit_lr_qr<2, 4>, (const void*)k_fit_lr_qr<4, 8>, (const void*)k_fit_lr_qr<0, 0>,
+                       (const void*)k_fit_rl_lq<2, 4>, (const void*)k_fit_rl_lq<4, 8>, (const void*)k_fit_rl_lq<0, 0>};
+  hipError_t e = hipSuccess;
+  for (const void* f : fns)
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   return e;
 }
 }  // namespace qtt_solver_detail

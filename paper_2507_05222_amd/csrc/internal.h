@@ -43,7 +43,7 @@ struct Geo {
 
 // Kernel classes of the measurement hook (qtt_timer_start / qtt_timer_read).
 enum KClass {
-  KC_ZIP_CONTRACT = 0,  // zip-up site contractions (carry.X_k, M_k.T1)
+  KC_ZIP_CONTRACT = 0,  // zip-up site contractions (carry.X_k, and M_k.T1 when fused)
   KC_ZIP_GRAM = 1,      // Gram products of the zip-up
   KC_ZIP_FACTOR = 2,    // Jacobi eigen-decomposition of the Gram matrix
   KC_ZIP_CARRY = 3,     // carry projection U^T Theta
@@ -97,6 +97,11 @@ void ws_init(const Batch& b, const WsLayout& wl, hipStream_t s);
 void zip_init(const Batch& b, const WsLayout& wl, hipStream_t s);
 void zip_t1(const Batch& b, const Geo& g, hipStream_t s);
 void zip_t2(const Batch& b, const Geo& g, hipStream_t s);
+// both zip-up contractions of a site: fused in one kernel (FP64, capx 64 or 128,
+// MPO bond <= 32) or zip_t1 then zip_t2; zip_contract_fused returns false if it
+// launched nothing
+void zip_contract(const Batch& b, const Geo& g, hipStream_t s);
+bool zip_contract_fused(const Batch& b, const Geo& g, hipStream_t s);
 void zip_gram(const Batch& b, const Geo& g, hipStream_t s);
 void zip_factor(const Batch& b, const Geo& g, hipStream_t s);
 void mpo_transpose(const Batch& b, const Geo& g, hipStream_t s);

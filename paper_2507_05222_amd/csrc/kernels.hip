@@ -87,6 +87,161 @@ __global__ void __launch_bounds__(256) k_zip_t2(Batch b, Geo g, WsLayout wl) {
                   m0, n0);
 }
 
+// Fused zip-up contraction of site k in FP64, one workgroup per output row a' of
+// one chain:
+//   stage 1: T1[bw][(s, c')] = sum_c carry[(a', bw)][c] X_k[c][(s, c')]
+//   stage 2: Theta[a'][(r', bw')][c'] = sum_{(bw, s)} Mt[(r', bw')][(bw, s)] T1[bw][(s, c')]
+// T1 stays in LDS: written to HBM and read back (k_zip_t1 then k_zip_t2) it makes the
+// MPO product a ~3 flop/byte stream, bound by bandwidth; fused, the site costs one
+// read of the carry and one write of Theta. MB: 16-row blocks of the MPO bonds
+// (w, w' <= 16 MB); the slot capacity is capx = 32 NB. Wave v owns T1 columns
+// [16 NB v, 16 NB (v + 1)) and Theta columns [8 NB v, 8 NB (v + 1)). Each product adds
+// its K terms in the order of gemm_tile, so Theta equals the two-kernel result bit
+// for bit.
+template <int MB, int NB>
+struct FusedShape {
+  static constexpr int CAP = 32 * NB;        // slot capacity of x
+  static constexpr int R = 16 * MB;          // rows of T1 (MPO bond, padded)
+  static constexpr int LDT = 48;             // row stride of the transposed carry block (As[c][bw])
+  static constexpr int S1 = CAP + 16;        // offset of the s = 1 half of a T1 row
+  static constexpr int LD = 2 * S1;          // row stride of T1 in LDS
+  static constexpr size_t bytes() {
+    const size_t a = (size_t)CAP * LDT, t = (size_t)R * LD;
+    return 8 * (a > t ? a : t);
+  }
+};
+
+template <int MB, int NB>
+__global__ void __launch_bounds__(256) k_zip_fused(Batch b, Geo g, WsLayout wl) {
+  using F = FusedShape<MB, NB>;
+  extern __shared__ double lds[];
+  const int ap = blockIdx.x, ci = blockIdx.y;
+  if (ci >= b.n) return;
+  Chain& c = b.c[ci];
+  const int k = g.k;
+  const int yb = c.yb[k], w = c.mb[k], w2 = c.mb[k + 1], K1 = c.xb[k], xb1 = c.xb[k + 1];
+  if (g.cnt && ap == 0 && threadIdx.x == 0) {
+    const double m1 = (double)yb * w, n1 = 2.0 * xb1, m2 = 2.0 * w2, k2 = 2.0 * w;
+    atomicAdd(g.cnt, 2.0 * m1 * n1 * K1 + yb * 2.0 * m2 * xb1 * k2);
+    atomicAdd(g.cnt + 1, 8.0 * (m1 * K1 + K1 * n1 + m1 * n1) + yb * 8.0 * (m2 * k2 + k2 * xb1 + m2 * xb1));
+  }
+  if (ap >= yb) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  // carry rows (a', bw), bw < w, transposed into As[c][bw]; zeros beyond w and K1
+  double* As = lds;
+  const gcdp carry = as_global((const double*)(c.ws + wl.carry)) + (long)ap * w * F::CAP;
+  const int K1p = (K1 + 3) & ~3;
+  for (int e = tid; e < K1p * F::R; e += 256) {
+    const int bw = e / K1p, cc = e % K1p;
+    As[cc * F::LDT + bw] = (bw < w && cc < K1) ? carry[(long)bw * F::CAP + cc] : 0.0;
+  }
+  __syncthreads();
+  // stage 1: this wave's T1 columns, X_k fragments straight from L2, four k-steps
+  // of loads in flight ahead of the MFMAs
+  const gcdp X = as_global(c.x) + (long)k * F::CAP * 2 * F::CAP;
+  const int col0 = wave * 16 * NB + li;
+  v4d acc[MB][NB];
+#pragma unroll
+  for (int u = 0; u < MB; ++u)
+#pragma unroll
+    for (int v = 0; v < NB; ++v) acc[u][v] = v4d{0, 0, 0, 0};
+  double bq[2][4][NB];
+  auto loadb = [&](int buf, int k0) {
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int kk = k0 + 4 * st + lk;
+#pragma unroll
+      for (int v = 0; v < NB; ++v) bq[buf][st][v] = (kk < K1) ? X[(long)kk * 2 * F::CAP + col0 + 16 * v] : 0.0;
+    }
+  };
+  auto mma = [&](int buf, int k0) {
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int kk = k0 + 4 * st;
+      if (kk < K1p) {
+        double a[MB];
+#pragma unroll
+        for (int u = 0; u < MB; ++u) a[u] = As[(kk + lk) * F::LDT + 16 * u + li];
+#pragma unroll
+        for (int u = 0; u < MB; ++u)
+#pragma unroll
+          for (int v = 0; v < NB; ++v)
+            acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bq[buf][st][v], acc[u][v], 0, 0, 0);
+      }
+    }
+  };
+  // two chunks of 16 per trip, so that the buffer index is a constant
+  loadb(0, 0);
+  for (int k0 = 0; k0 < K1p; k0 += 32) {
+    if (k0 + 16 < K1p) loadb(1, k0 + 16);
+    mma(0, k0);
+    if (k0 + 32 < K1p) loadb(0, k0 + 32);
+    if (k0 + 16 < K1p) mma(1, k0 + 16);
+  }
+  __syncthreads();   // every wave is done with As before T1 overwrites it
+  // stage-2 operand A = Mt (rows (r', bw') < 2 w', K = 2 w <= 2 R), read from L2
+  // four k-steps ahead of its use (the first four before the T1 exchange), so no
+  // k-step of stage 2 waits on a load
+  constexpr int MB2 = 2 * MB, NB2 = NB / 2, KS2 = (2 * 16 * MB) / 4, AH = 4;
+  const gcdp Mt = as_global((const double*)(c.ws + wl.mt)) + (size_t)k * (2 * g.W) * (2 * g.W);
+  const int M2 = 2 * w2, K2 = 2 * w;
+  double a2[AH][MB2];
+  auto load_a2 = [&](int slot, int st) {
+#pragma unroll
+    for (int u = 0; u < MB2; ++u) {
+      const int m = 16 * u + li, kk = 4 * st + lk;
+      a2[slot][u] = (m < M2 && kk < K2) ? Mt[(long)m * K2 + kk] : 0.0;
+    }
+  };
+#pragma unroll
+  for (int st = 0; st < AH; ++st) load_a2(st, st);
+  double* T1 = lds;
+#pragma unroll
+  for (int u = 0; u < MB; ++u)
+#pragma unroll
+    for (int v = 0; v < NB; ++v)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = 16 * u + lk + 4 * q, col = wave * 16 * NB + 16 * v + li;   // col = s CAP + c'
+        const int sh = col >= F::CAP ? 1 : 0;
+        T1[row * F::LD + sh * F::S1 + (col - sh * F::CAP)] = acc[u][v][q];
+      }
+  __syncthreads();
+  // stage 2: Theta rows (r', bw') < 2 w', this wave's columns
+  v4d acc2[MB2][NB2];
+#pragma unroll
+  for (int u = 0; u < MB2; ++u)
+#pragma unroll
+    for (int v = 0; v < NB2; ++v) acc2[u][v] = v4d{0, 0, 0, 0};
+  const int n0 = wave * 8 * NB;
+#pragma unroll
+  for (int st = 0; st < KS2; ++st) {
+    if (4 * st < K2) {
+      const int kk = 4 * st + lk;
+      double bb[NB2];
+#pragma unroll
+      for (int v = 0; v < NB2; ++v) bb[v] = T1[(kk >> 1) * F::LD + (kk & 1) * F::S1 + n0 + 16 * v + li];
+#pragma unroll
+      for (int u = 0; u < MB2; ++u)
+#pragma unroll
+        for (int v = 0; v < NB2; ++v)
+          acc2[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[st % AH][u], bb[v], acc2[u][v], 0, 0, 0);
+      if (st + AH < KS2) load_a2(st % AH, st + AH);
+    }
+  }
+  const gdp th = as_global(c.ws + wl.theta) + (long)ap * M2 * F::CAP;
+#pragma unroll
+  for (int u = 0; u < MB2; ++u)
+#pragma unroll
+    for (int v = 0; v < NB2; ++v)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = 16 * u + lk + 4 * q;
+        if (m < M2) th[(long)m * F::CAP + n0 + 16 * v + li] = acc2[u][v][q];
+      }
+}
+
 // Gram G = Theta Theta^T (FP64), split over K into wl.splits partial products.
 __global__ void __launch_bounds__(256) k_zip_gram(Batch b, Geo g, WsLayout wl) {
   const int ci = blockIdx.z / wl.splits, sp = blockIdx.z % wl.splits;
@@ -527,6 +682,10 @@ hipError_t init(int lds_bytes) {
   hipError_t e = hipFuncSetAttribute((const void*)k_zip_factor, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_rl_svd, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_lr_qr, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  const void* fused[] = {(const void*)k_zip_fused<1, 2>, (const void*)k_zip_fused<1, 4>, (const void*)k_zip_fused<2, 2>,
+                         (const void*)k_zip_fused<2, 4>};
+  for (const void* f : fused)
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
   return e;
 }
 
@@ -552,6 +711,34 @@ void zip_t1(const Batch& b, const Geo& g, hipStream_t s) {
   else if (g.mode == 1) hipLaunchKernelGGL(k_zip_t1<1>, grid, dim3(256), 0, s, b, gg, wl);
   else hipLaunchKernelGGL(k_zip_t1<2>, grid, dim3(256), 0, s, b, gg, wl);
   tmark(KC_ZIP_CONTRACT, s);
+}
+
+template <int MB, int NB>
+void launch_fused(const Batch& b, const Geo& g, hipStream_t s) {
+  hipLaunchKernelGGL((k_zip_fused<MB, NB>), dim3(g.capy, b.n), dim3(256), (FusedShape<MB, NB>::bytes()), s, b, g, lay(g));
+}
+
+bool zip_contract_fused(const Batch& b, const Geo& g, hipStream_t s) {
+  if (g.mode != 0 || g.W > 32 || (g.capx != 64 && g.capx != 128)) return false;
+  const int mb = g.W <= 16 ? 1 : 2, nb = g.capx / 32;
+  const size_t need = mb == 1 ? (nb == 2 ? FusedShape<1, 2>::bytes() : FusedShape<1, 4>::bytes())
+                              : (nb == 2 ? FusedShape<2, 2>::bytes() : FusedShape<2, 4>::bytes());
+  if (need > (size_t)g.lds) return false;
+  Geo gg = g;
+  tmark(KC_ZIP_CONTRACT, s);
+  gg.cnt = tcount(KC_ZIP_CONTRACT);
+  if (mb == 1 && nb == 2) launch_fused<1, 2>(b, gg, s);
+  else if (mb == 1) launch_fused<1, 4>(b, gg, s);
+  else if (nb == 2) launch_fused<2, 2>(b, gg, s);
+  else launch_fused<2, 4>(b, gg, s);
+  tmark(KC_ZIP_CONTRACT, s);
+  return true;
+}
+
+void zip_contract(const Batch& b, const Geo& g, hipStream_t s) {
+  if (zip_contract_fused(b, g, s)) return;
+  zip_t1(b, g, s);
+  zip_t2(b, g, s);
 }
 
 void zip_t2(const Batch& b, const Geo& g, hipStream_t s) {

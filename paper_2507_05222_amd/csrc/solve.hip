@@ -316,6 +316,7 @@ __global__ void __launch_bounds__(1024) k_cg_step(SBatch sb, SGeo g, SLay l) {
 
 // Right-to-left gauge move at site k by Householder LQ (bond kept):
 // Y_k (b_k x 2 b_{k+1}): Y_k^T = Q R  ->  core k <- Q^T, Y_{k-1} <- Y_{k-1} R^T.
+template <int RPL, int CPW>
 __global__ void __launch_bounds__(1024) k_rl_qr(SBatch sb, SGeo g, SLay l) {
   extern __shared__ double smem[];
   __shared__ double rdiag[512], tau[512], vbuf[1024];
@@ -324,7 +325,7 @@ __global__ void __launch_bounds__(1024) k_rl_qr(SBatch sb, SGeo g, SLay l) {
   const int k = g.k, cap = g.cx;
   const int nb = c.xb[k], mb = c.xb[k + 1];
   const int m = 2 * mb, n = nb, r = m < n ? m : n;
-  const bool fast = (m <= 256 && n <= 128);
+  const bool fast = RPL > 0 && m <= 64 * RPL && n <= 16 * CPW;
   const size_t need = ((size_t)m * n + (fast ? 0 : (size_t)m * r)) * sizeof(double);
   // The budget passed in smem size is checked by the host; fall back to global scratch otherwise.
   double* X = (need <= (size_t)g.lds) ? smem : (c.ws + l.gp);
@@ -338,8 +339,7 @@ __global__ void __launch_bounds__(1024) k_rl_qr(SBatch sb, SGeo g, SLay l) {
   if (fast) {
     for (int e = threadIdx.x; e < S; e += blockDim.x) Yk[e] = 0.0;
     auto qs = [&](int rho, int j, double v) { Yk[(long)j * 2 * cap + (rho / mb) * cap + rho % mb] = v; };
-    if (m <= 128 && n <= 64) qr_regs<2, 4>(X, m, n, rdiag, tau, vbuf, qs);
-    else qr_regs<4, 8>(X, m, n, rdiag, tau, vbuf, qs);
+    if constexpr (RPL > 0) qr_regs<RPL, CPW>(X, m, n, rdiag, tau, vbuf, qs);
   } else {
     double* Q = X + (size_t)m * n;
     householder(X, m, n, rdiag, tau);
@@ -367,6 +367,7 @@ __global__ void __launch_bounds__(1024) k_rl_qr(SBatch sb, SGeo g, SLay l) {
 
 // Left-to-right gauge move at site k by Householder QR (bond kept):
 // core k (2 b_k x b_{k+1}) = Q R -> core k <- Q, core k+1 <- R core k+1.
+template <int RPL, int CPW>
 __global__ void __launch_bounds__(1024) k_lr_qr_keep(SBatch sb, SGeo g, SLay l) {
   extern __shared__ double smem[];
   __shared__ double rdiag[512], tau[512], vbuf[1024];
@@ -375,7 +376,7 @@ __global__ void __launch_bounds__(1024) k_lr_qr_keep(SBatch sb, SGeo g, SLay l) 
   const int k = g.k, cap = g.cx;
   const int m = 2 * c.xb[k], n = c.xb[k + 1];
   const int r = m < n ? m : n;
-  const bool fast = (m <= 256 && n <= 128);
+  const bool fast = RPL > 0 && m <= 64 * RPL && n <= 16 * CPW;
   const size_t need = ((size_t)m * n + (fast ? 0 : (size_t)m * r)) * sizeof(double);
   double* X = (need <= (size_t)g.lds) ? smem : (c.ws + l.gp);
   double* Yk = c.x + (long)k * sl2(cap);
@@ -388,8 +389,7 @@ __global__ void __launch_bounds__(1024) k_lr_qr_keep(SBatch sb, SGeo g, SLay l) 
   if (fast) {
     for (int e = threadIdx.x; e < S; e += blockDim.x) Yk[e] = 0.0;
     auto qs = [&](int i, int j, double v) { Yk[(long)i * cap + j] = v; };
-    if (m <= 128 && n <= 64) qr_regs<2, 4>(X, m, n, rdiag, tau, vbuf, qs);
-    else qr_regs<4, 8>(X, m, n, rdiag, tau, vbuf, qs);
+    if constexpr (RPL > 0) qr_regs<RPL, CPW>(X, m, n, rdiag, tau, vbuf, qs);
   } else {
     double* Q = X + (size_t)m * n;
     householder(X, m, n, rdiag, tau);
@@ -695,14 +695,18 @@ struct Solver {
     SGeo gg = g;
     gg.k = k;
     qttk::tmark(KC_LR_QR, s);
-    hipLaunchKernelGGL(k_lr_qr_keep, dim3(sb.n), dim3(1024), lds, s, sb, gg, l);
+    if (g.cx <= 64) hipLaunchKernelGGL((k_lr_qr_keep<2, 4>), dim3(sb.n), dim3(1024), lds, s, sb, gg, l);
+    else if (g.cx <= 128) hipLaunchKernelGGL((k_lr_qr_keep<4, 8>), dim3(sb.n), dim3(1024), lds, s, sb, gg, l);
+    else hipLaunchKernelGGL((k_lr_qr_keep<0, 0>), dim3(sb.n), dim3(1024), lds, s, sb, gg, l);
     qttk::tmark(KC_LR_QR, s);
   }
   void rl_move(int k) {
     SGeo gg = g;
     gg.k = k;
     qttk::tmark(KC_LR_QR, s);
-    hipLaunchKernelGGL(k_rl_qr, dim3(sb.n), dim3(1024), lds, s, sb, gg, l);
+    if (g.cx <= 64) hipLaunchKernelGGL((k_rl_qr<2, 4>), dim3(sb.n), dim3(1024), lds, s, sb, gg, l);
+    else if (g.cx <= 128) hipLaunchKernelGGL((k_rl_qr<4, 8>), dim3(sb.n), dim3(1024), lds, s, sb, gg, l);
+    else hipLaunchKernelGGL((k_rl_qr<0, 0>), dim3(sb.n), dim3(1024), lds, s, sb, gg, l);
     qttk::tmark(KC_LR_QR, s);
   }
 };
@@ -723,8 +727,11 @@ double* pinned(qtt_ctx* ctx, size_t doubles, int* rc);
 
 namespace qtt_solver_detail {
 hipError_t solver_init(int lds) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_rl_qr, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_lr_qr_keep, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  const void* fns[] = {(const void*)k_rl_qr<2, 4>, (const void*)k_rl_qr<4, 8>, (const void*)k_rl_qr<0, 0>,
+                       (const void*)k_lr_qr_keep<2, 4>, (const void*)k_lr_qr_keep<4, 8>, (const void*)k_lr_qr_keep<0, 0>};
+  hipError_t e = hipSuccess;
+  for (const void* f : fns)
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   return e;
 }
 }

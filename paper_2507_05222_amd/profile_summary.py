@@ -1,0 +1,77 @@
+#!/usr/bin/env python3
+"""Traffic summary of the batched GEMM kernel from rocprofv3 counter runs.
+
+Reads the rocpd databases of four `rocprofv3 --pmc` runs (FETCH_SIZE and WRITE_SIZE
+of the benchmark, and of a plain 256 MiB device copy for calibration) and the
+kernel-trace database of the same benchmark command, and writes the JSON that
+bench.py reports as `roofline.traffic` (HBM bytes per launch of k_gemm_jobs<0, *>,
+both tile sizes) next to the trace's average launch duration.
+
+  python -m paper_2507_05222_amd.profile_summary --fetch F.db --write W.db \\
+      --cal-fetch CF.db --cal-write CW.db --trace T.db --out profiles/....json
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sqlite3
+
+KERNEL = "k_gemm_jobs<0,"
+COPY_KIB = 262144.0      # 2^25 doubles
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SOURCES = [os.path.join(ROOT, "paper_2507_05222_amd", "csrc", f) for f in ("gemm_jobs.h", "device_common.h")]
+
+
+def counter(db, name, pattern):
+    """(dispatches, mean counter value in KiB) over kernels whose name contains pattern."""
+    c = sqlite3.connect(db)
+    rows = c.execute("select count(*), avg(counter_value) from pmc_events where counter_name = ? and "
+                     "replace(name, ' ', '') like ?", (name, f"%{pattern.replace(' ', '')}%")).fetchone()
+    return int(rows[0]), float(rows[1] or 0.0)
+
+
+def trace_avg_us(db, pattern):
+    c = sqlite3.connect(db)
+    r = c.execute("select count(*), avg(end - start) from kernels where replace(name, ' ', '') like ?",
+                  (f"%{pattern.replace(' ', '')}%",)).fetchone()
+    return int(r[0]), float(r[1] or 0.0) / 1e3
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    for a in ("fetch", "write", "cal_fetch", "cal_write", "trace", "out"):
+        ap.add_argument("--" + a.replace("_", "-"), required=True)
+    ap.add_argument("--workload", default="cylinder O-grid 2^10x2^10, chi=64, fast path, one step (warm-up 0)")
+    a = ap.parse_args()
+    nf, fetch = counter(a.fetch, "FETCH_SIZE", KERNEL)
+    nw, write = counter(a.write, "WRITE_SIZE", KERNEL)
+    _, cf = counter(a.cal_fetch, "FETCH_SIZE", "copyBuffer")
+    _, cw = counter(a.cal_write, "WRITE_SIZE", "copyBuffer")
+    nt, avg = trace_avg_us(a.trace, KERNEL)
+    out = {
+        "kernel": "k_gemm_jobs<0, 32|64> (FP64 MFMA batched contractions, both tile sizes)",
+        "workload": a.workload,
+        "dispatches": nf, "dispatches_write_run": nw,
+        "fetch_kib_per_dispatch": round(fetch, 3), "write_kib_per_dispatch": round(write, 3),
+        "copy_kib": COPY_KIB, "copy_fetch_kib": cf, "copy_write_kib": cw,
+        "fetch_factor": round(COPY_KIB / cf, 4), "write_factor": round(COPY_KIB / cw, 4),
+        "kernel_source_sha256_16": source_hash(),
+        "kernel_trace_avg_us": round(avg, 2), "kernel_trace_dispatches": nt,
+    }
+    with open(a.out, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -92,6 +92,24 @@ def test_apply_truncated_smooth_field(Q, ctx):
         assert max(y.bonds()) <= chi
 
 
+@pytest.mark.parametrize("cap", [64, 128])
+def test_apply_fused_contraction_exact(Q, ctx, cap):
+    """FP64 apply at slot capacities 64 and 128, where both contractions of a site run
+    in one kernel: MPO bonds 3 and 20 (one and two 16-row blocks) in one batch, ragged
+    bonds (L = 12: 1, 2, .., 64, .., 2, 1) below the capacity; exact product."""
+    L = 12
+    xs = [random_mps_cores(L, cap, seed=30 + i) for i in range(2)]
+    Ms = [random_mpo_cores(L, w, seed=40 + i) for i, w in enumerate((3, 20))]
+    X = [_rc(Q, ctx, c, cap) for c in xs]
+    Y = [Q.MPS(L, 64) for _ in range(2)]
+    mpos = [Q.MPO.from_cores(m, wcap=20) for m in Ms]
+    Q.apply_mpo(ctx, mpos, X, Y, tol=0.0, chi=64)
+    for i in range(2):
+        ref = R.mpo_apply_dense(Ms[i], R.tt_full(xs[i]))
+        assert rel(R.tt_full(Y[i].cores()), ref) < 1e-10
+        assert right_orthonormal_error(Y[i].cores()) < 1e-10
+
+
 def test_apply_batched_matches_single(Q, ctx):
     L = 10
     xs = [random_mps_cores(L, 6, seed=10 + i) for i in range(3)]

@@ -50,7 +50,11 @@ def test_step_warm_start_is_per_state():
     F.fractional_step(shared, ops, b, opts)
     b_ref = state(2)
     F.fractional_step(Q.Context(0), ops, b_ref, opts)
+    # Split products add their partial sums with atomic adds in no fixed order, so two
+    # identical steps agree to rounding amplified by the solves (~1e-12), not bit for
+    # bit; a warm start taken from the other state changes the truncated fits by their
+    # truncation error, orders of magnitude above the bound.
     for name in ("u", "v", "p"):
         x = R.tt_full(getattr(b, name).cores())
         y = R.tt_full(getattr(b_ref, name).cores())
-        assert np.linalg.norm(x - y) <= 1e-12 * np.linalg.norm(y), name
+        assert np.linalg.norm(x - y) <= 1e-9 * np.linalg.norm(y), name
