@@ -35,7 +35,7 @@ sys.path.insert(0, ROOT)
 
 PEAKS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # dense TFLOP/s, MI355X published
 TRAFFIC = os.path.join(ROOT, "profiles", "k_gemm_jobs_f64_cylinder_2e20_chi64_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_05222_amd", "csrc", f) for f in ("gemm_jobs.h", "device_common.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_05222_amd", "csrc", f) for f in ("gemm_jobs.h", "gemm_tile.h")]
 
 
 def kernel_source_hash():
@@ -338,7 +338,7 @@ def main():
         prof = measured_profile()
         roof = {"bound": "mfma", "achieved": round(ach, 4), "peak": PEAKS["f64"], "unit": "TFLOP/s",
                 "frac": round(ach / PEAKS["f64"], 6), "traffic": None if prof is None else round(prof["traffic"], 1),
-                "kernel": "k_gemm_jobs<0> (batched FP64 MFMA site/environment contractions)",
+                "kernel": "k_gemm_jobs<0, 32|64> (batched FP64 MFMA site/environment contractions, both tile sizes)",
                 "avg_launch_us": round(1e3 * kt["ms"] / kt["launches"], 3), "launches": kt["launches"],
                 "timing": "HIP-event bracket per launch (includes its dispatch: an upper bound)",
                 "kernel_trace_avg_us": None if prof is None else prof["trace_avg_us"],

@@ -21,7 +21,7 @@ import sqlite3
 KERNEL = "k_gemm_jobs<0,"
 COPY_KIB = 262144.0      # 2^25 doubles
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SOURCES = [os.path.join(ROOT, "paper_2507_05222_amd", "csrc", f) for f in ("gemm_jobs.h", "device_common.h")]
+SOURCES = [os.path.join(ROOT, "paper_2507_05222_amd", "csrc", f) for f in ("gemm_jobs.h", "gemm_tile.h")]
 
 
 def counter(db, name, pattern):
