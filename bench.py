@@ -134,6 +134,27 @@ def sweep(args):
                 tf = (a["gflop"] + b["gflop"]) / max(tot_ms, 1e-9)
                 rec["contraction"] = {"tflops": round(tf, 3), "frac_of_peak": round(tf / PEAKS[dt], 5)}
                 rec["fused"] = b["launches"] == 0 and a["launches"] > 0
+                if rec["fused"]:
+                    # the fused kernel per site: work from the actual bonds (the zip-up's
+                    # output bonds are those of y, which the final sweep at tol 0 keeps),
+                    # time from the per-launch brackets of the last timed apply of class 0
+                    timer = Q.KernelTimer(ctx, "zip_contract", dt)
+                    timer.start()
+                    Q.apply_mpo(ctx, Ms, xs, ys, tol=0.0, chi=chi, dtype=dt, fit=0)
+                    timer.read()
+                    per = timer.durations()
+                    xb = [min(2 ** k, 2 ** (L - k), chi) for k in range(L + 1)]
+                    yb = ys[0].bonds()
+                    wb = [1] + [w] * (L - 1) + [1]
+                    sat = [k for k in range(L) if xb[k] == chi and xb[k + 1] == chi]
+                    fl = sum(args.trials * (4.0 * yb[k] * wb[k] * xb[k + 1] * xb[k] +
+                                            8.0 * yb[k] * wb[k + 1] * xb[k + 1] * wb[k]) for k in sat)
+                    ms = sum(per[k] for k in sat)
+                    tfs = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+                    rec["contraction_saturated_sites"] = {"sites": [sat[0], sat[-1]] if sat else [],
+                                                          "tflops": round(tfs, 3),
+                                                          "frac_of_peak": round(tfs / PEAKS[dt], 5),
+                                                          "avg_us": round(1e3 * ms / max(len(sat), 1), 2)}
                 print(json.dumps(rec), flush=True)
             del Ms, ys
             torch.cuda.empty_cache()

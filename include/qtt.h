@@ -272,12 +272,14 @@ int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_flow_state* s
  * While a kernel class is selected, every launch of that class is bracketed by
  * HIP events on its stream, and its GEMM-type kernels add their algorithmic work
  * (2 M N K flops and 8 (M K + K N + M N) bytes per product, with the actual bond
- * dimensions) to device counters. Classes: 0 zip-up site contractions, 1 zip-up
- * Gram products, 2 zip-up Jacobi factorisation, 3 zip-up carry projection,
- * 4 right-to-left Jacobi SVD sites, 5 Householder QR/LQ moves, 6 environment /
- * local-matvec / projection GEMMs on FP64 MFMA, 7 local CG updates, 8 the GEMMs
- * of class 6 on FP32 or BF16 MFMA, 9 zip-up contraction with the MPO core (class
- * 0 is then the carry-times-core product alone); -1 stops timing.
+ * dimensions) to device counters. Classes: 0 zip-up site contractions (both
+ * products of a site in one kernel in FP64 at slot capacity 64 or 128 with MPO
+ * bond <= 32; otherwise the carry-times-core product alone), 1 zip-up Gram
+ * products, 2 zip-up Jacobi factorisation, 3 zip-up carry projection, 4
+ * right-to-left Jacobi SVD sites, 5 Householder QR/LQ moves, 6 environment /
+ * local-matvec / projection GEMMs on FP64 MFMA, 7 local CG updates, 8 the GEMMs of
+ * class 6 on FP32 or BF16 MFMA, 9 zip-up product with the MPO core when it is not
+ * fused into class 0; -1 stops timing.
  * qtt_timer_read synchronises the device and returns the number of timed
  * launches, the summed duration of their event brackets (ms), the counted work,
  * and, for reference, the mean duration of the same bracket around an empty
@@ -285,6 +287,10 @@ int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_flow_state* s
  * the kernel, so ms / launches bounds the kernel's own duration from above. */
 int qtt_timer_start(qtt_ctx* ctx, int kernel_class);
 int qtt_timer_read(qtt_ctx* ctx, int64_t* launches, double* ms, double* flops, double* bytes, double* overhead_ms);
+/* Durations (ms) of the individual brackets of the last timed class, in launch
+ * order: ms (host, cap entries) receives the first min(cap, launches) of them and
+ * *n their number. Valid after qtt_timer_read until the next qtt_timer_start. */
+int qtt_timer_durations(qtt_ctx* ctx, double* ms, int64_t cap, int64_t* n);
 
 /* ---- host-side operator construction (setup, FP64, no GPU) ----------------
  * Builds, on the host, the TT cores of the operators and boundary vectors of a

@@ -559,3 +559,17 @@ extern "C" int qtt_timer_read(qtt_ctx* ctx, int64_t* launches, double* ms, doubl
   t.kc = -1;
   return QTT_OK;
 }
+
+extern "C" int qtt_timer_durations(qtt_ctx* ctx, double* ms, int64_t cap, int64_t* n) {
+  if (!ctx || !n || cap < 0 || (cap > 0 && !ms)) return QTT_EINVAL;
+  qttk::Timer& t = qttk::timer();
+  HIPCHK(ctx, hipDeviceSynchronize());
+  const int64_t have = (int64_t)(t.used / 2);
+  *n = have < cap ? have : cap;
+  for (int64_t i = 0; i < *n; ++i) {
+    float e = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&e, t.ev[2 * i], t.ev[2 * i + 1]));
+    ms[i] = e;
+  }
+  return QTT_OK;
+}

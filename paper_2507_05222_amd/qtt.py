@@ -122,6 +122,7 @@ def lib():
         L.qtt_timer_start.argtypes = [vp, i32]
         L.qtt_timer_read.argtypes = [vp, p(ctypes.c_int64), p(ctypes.c_double), p(ctypes.c_double),
                                      p(ctypes.c_double), p(ctypes.c_double)]
+        L.qtt_timer_durations.argtypes = [vp, p(ctypes.c_double), ctypes.c_int64, p(ctypes.c_int64)]
         L.qtt_build_host.argtypes = [p(CCylinder), i32, ctypes.c_int32, vp, vp, p(ctypes.c_int32)]
         L.qtt_tt_svd_host.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, p(CTrunc), ctypes.c_int32, vp, vp]
         L.qtt_ws_act_floats.argtypes = [i32]
@@ -424,3 +425,10 @@ class KernelTimer:
         launches = int(n.value)
         return {"name": self.name, "dtype": self.dtype, "launches": launches, "ms": ms.value,
                 "idle_bracket_ms": ov.value, "flops": fl.value, "bytes": by.value}
+
+    def durations(self, cap: int = 4096):
+        """Per-launch bracket durations (ms) of the last read, in launch order."""
+        buf = (ctypes.c_double * cap)()
+        n = ctypes.c_int64(0)
+        self.ctx.check(lib().qtt_timer_durations(self.ctx.h, buf, cap, ctypes.byref(n)))
+        return [buf[i] for i in range(n.value)]
