@@ -324,7 +324,7 @@ def main():
             meta = json.load(f)
         print("[bench] learned warm start vs cold start", file=sys.stderr, flush=True)
         warm = {"held_out_rel_l2_coarse": meta["held_out_rel_l2"], "cases": []}
-        for re_, al in meta["test_configs"][:2]:
+        for re_, al in meta["test_configs"]:
             r = W.compare_cold_learned(ctx, re_, al)
             warm["cases"].append({"Re": round(re_, 2), "alpha": round(al, 3),
                                   "cold": {k: r["cold"][k] for k in ("cg_iters", "sweeps", "step_s")},
