@@ -276,6 +276,270 @@ __device__ __forceinline__ void jacobi_cols(double* X, int m, int ldx, int n, do
   }
 }
 
+// ---------------------------------------------------------------------------
+// Symmetric eigen-decomposition for one workgroup (1024 threads): Householder
+// reduction to tridiagonal form, explicit accumulation of its orthogonal factor,
+// then the implicit QL iteration with Wilkinson shifts on the tridiagonal matrix
+// (the textbook method, e.g. Golub & Van Loan, Matrix Computations, Sec. 8.3).
+// G: m x m symmetric, both triangles stored, column j at G + j*ldg; overwritten.
+// On exit lam[i] is an eigenvalue and column i of Z (Z + i*ldz) its unit
+// eigenvector, unordered. lam and work (6 m doubles) should be in LDS; Z may be in
+// global memory. m <= 960 (one thread of the last wavefront runs the scalar QL
+// recurrence while the first ceil(m/64) wavefronts rotate the rows of Z).
+// ---------------------------------------------------------------------------
+__device__ void sym_eig(double* G, int m, int ldg, double* Z, int ldz, double* lam, double* work) {
+  __shared__ int nrot[2], top[2];
+  __shared__ double psum[1024];                   // partial sums of the tridiagonalisation matvec
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  double* e = work;             // sub-diagonal: e[i] couples i and i + 1
+  double* tau = work + m;       // reflector factors
+  double* v = work + 2 * m;     // current reflector
+  double* pw = work + 3 * m;    // p = tau A v, then w = p - (tau/2)(p.v) v
+  double* rc = work + 4 * m;    // cosines and sines of the Givens rotations of one QL
+  double* rs = work + 5 * m;    // iteration; v and pw (free by then) hold the other buffer
+  // --- 1. tridiagonalisation: H_j = I - tau_j v_j v_j^T acts on rows/columns j+1..m-1
+  for (int j = 0; j + 2 < m; ++j) {
+    const int n2 = m - j - 1;
+    double* x = G + (long)j * ldg + j + 1;          // column j below the diagonal
+    if (wave == 0) {
+      double mx = 0.0, ss = 0.0;
+      for (int i = lane; i < n2; i += 64) { const double t = x[i]; mx = fmax(mx, fabs(t)); ss += t * t; }
+      mx = wave_max(mx);
+      ss = wave_sum(ss);
+      const bool live = mx > HH_TINY;
+      const bool rescale = live && !(mx > HH_SMALL && mx < HH_BIG);
+      const double sc = !live ? 0.0 : (rescale ? 1.0 / mx : 1.0);
+      if (rescale) {
+        ss = 0.0;
+        for (int i = lane; i < n2; i += 64) { const double t = x[i] * sc; ss += t * t; }
+        ss = wave_sum(ss);
+      }
+      const double x0 = x[0] * sc;
+      double alpha = 0.0, tj = 0.0, v0 = 0.0;
+      if (live) {
+        alpha = x0 >= 0 ? -sqrt(ss) : sqrt(ss);
+        v0 = x0 - alpha;
+        const double vv = ss - x0 * x0 + v0 * v0;
+        tj = vv > 0.0 ? 2.0 / vv : 0.0;
+      }
+      for (int i = lane; i < n2; i += 64) {
+        const double vi = (i == 0) ? v0 : x[i] * sc;
+        v[j + 1 + i] = vi;
+        x[i] = vi;                                   // kept for the accumulation of Q
+      }
+      if (lane == 0) {
+        tau[j] = tj;
+        lam[j] = G[(long)j * ldg + j];
+        e[j] = live ? (rescale ? alpha * mx : alpha) : x0;   // x0 = 0 when not live
+      }
+    }
+    __syncthreads();
+    const double tj = tau[j];
+    if (tj != 0.0) {
+      // p_i = tau sum_k A(i, k) v_k over the trailing block: thread (part, row) sums
+      // its part of k for row i; consecutive threads read consecutive rows of each
+      // column (coalesced), and the loads of a thread are independent of each other
+      {
+        const int RS = m <= 256 ? 256 : 512, parts = (int)blockDim.x / RS;
+        const int r = tid % RS, part = tid / RS, i = j + 1 + r;
+        const int kl = (n2 + parts - 1) / parts, k0 = j + 1 + part * kl, k1 = min(m, k0 + kl);
+        double a = 0.0;
+        if (i < m)
+          for (int k = k0; k < k1; ++k) a += G[(long)k * ldg + i] * v[k];
+        psum[part * RS + r] = a;
+        __syncthreads();
+        if (tid < n2) {
+          double t = 0.0;
+          for (int q = 0; q < parts; ++q) t += psum[q * RS + tid];
+          pw[j + 1 + tid] = tj * t;
+        }
+      }
+      __syncthreads();
+      double pv = 0.0;
+      if (wave == 0) {
+        for (int i = j + 1 + lane; i < m; i += 64) pv += pw[i] * v[i];
+        pv = wave_sum(pv);
+      }
+      __syncthreads();
+      if (wave == 0) {
+        const double K = 0.5 * tj * pv;
+        for (int i = j + 1 + lane; i < m; i += 64) pw[i] -= K * v[i];
+      }
+      __syncthreads();
+      // A -= v w^T + w v^T on the trailing block
+      for (long q = tid; q < (long)n2 * n2; q += blockDim.x) {
+        const int k = j + 1 + (int)(q / n2), i = j + 1 + (int)(q % n2);
+        G[(long)k * ldg + i] -= v[i] * pw[k] + pw[i] * v[k];
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    if (m >= 2) {
+      lam[m - 2] = G[(long)(m - 2) * ldg + m - 2];
+      e[m - 2] = G[(long)(m - 2) * ldg + m - 1];
+      tau[m - 2] = 0.0;
+    }
+    lam[m - 1] = G[(long)(m - 1) * ldg + m - 1];
+    e[m - 1] = 0.0;
+    tau[m - 1] = 0.0;
+  }
+  // --- 2. Q = H_0 H_1 ... H_{m-3}, accumulated backwards into Z (starting from I)
+  for (long q = tid; q < (long)m * m; q += blockDim.x) Z[(q / m) * ldz + q % m] = (q / m == q % m) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int j = m - 3; j >= 0; --j) {
+    const double tj = tau[j];
+    if (tj == 0.0) continue;
+    const double* vj = G + (long)j * ldg;          // v_j in rows j+1..m-1 of column j
+    // s_c = tau v^T Z(:, c): four columns per wavefront at a time, their loads issued
+    // together and their sums reduced together
+    for (int c0 = j + 1 + 4 * wave; c0 < m; c0 += 4 * nw) {
+      double a[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int i = j + 1 + lane; i < m; i += 64) {
+        const double vi = vj[i];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (c0 + u < m) a[u] += vi * Z[(long)(c0 + u) * ldz + i];
+      }
+      wave_sum_n<4>(a);
+      if (lane < 4 && c0 + lane < m) pw[c0 + lane] = tj * (lane == 0 ? a[0] : lane == 1 ? a[1] : lane == 2 ? a[2] : a[3]);
+    }
+    __syncthreads();
+    const int n2 = m - j - 1;
+    for (long q = tid; q < (long)n2 * n2; q += blockDim.x) {
+      const int c = j + 1 + (int)(q / n2), i = j + 1 + (int)(q % n2);
+      Z[(long)c * ldz + i] -= vj[i] * pw[c];
+    }
+    __syncthreads();
+  }
+  // --- 3. implicit QL on (lam, e); the rotations of each iteration are applied to
+  // the columns of Z by the row threads while the last wavefront computes the next
+  // iteration (ping-pong buffers (rc, rs) and (v, pw), up to m - 1 rotations each).
+  // The whole last wavefront runs the recurrence in lock-step (lane 0 stores), so the
+  // search for a negligible sub-diagonal element is a 64-wide ballot. The matrix is
+  // scaled to norm <= 1 first, which makes sqrt(f^2 + g^2) safe in place of hypot.
+  const bool scalar = (wave == nw - 1);
+  __shared__ double qscale;
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int i = 0; i < m; ++i) mx = fmax(mx, fabs(lam[i]) + 2.0 * fabs(e[i]));
+    qscale = mx > 0.0 ? mx : 1.0;
+  }
+  __syncthreads();
+  {
+    const double inv = 1.0 / qscale;
+    for (int i = tid; i < m; i += blockDim.x) { lam[i] *= inv; e[i] *= inv; }
+  }
+  __syncthreads();
+  int ql_l = 0, ql_it = 0;                        // state of the QL wavefront (uniform)
+  auto produce = [&](int b) {
+    // one QL iteration (or the end); rotations for columns (i, i+1), i = top, top-1, ...
+    double* cb = b ? v : rc;
+    double* sb = b ? pw : rs;
+    int cnt = -1, tp = 0;
+    const double eps = 2.220446049250313e-16;
+    while (ql_l < m) {
+      const int l = ql_l;
+      int mm = m - 1;
+      for (int q0 = l; q0 < m - 1; q0 += 64) {
+        const int q = q0 + lane;
+        const bool small = q < m - 1 && fabs(e[q]) <= eps * (fabs(lam[q]) + fabs(lam[q + 1]));
+        const unsigned long long mask = __ballot(small);
+        if (mask) { mm = q0 + __ffsll((long long)mask) - 1; break; }
+      }
+      if (mm == l || ql_it >= 60) { ql_l++; ql_it = 0; continue; }
+      ++ql_it;
+      double g = (lam[l + 1] - lam[l]) / (2.0 * e[l]);
+      double r = sqrt(g * g + 1.0);
+      g = lam[mm] - lam[l] + e[l] / (g + (g >= 0 ? r : -r));
+      double sn = 1.0, cs = 1.0, p = 0.0;
+      cnt = 0;
+      tp = mm - 1;
+      bool under = false;
+      double lam_up = lam[mm];                    // lam[i + 1] of the current step (old value)
+      double ei = e[mm - 1], li = lam[mm - 1];     // e[i], lam[i] of the current step
+      for (int i = mm - 1; i >= l; --i) {
+        // operands of the next step, loaded ahead (not written by this iteration yet)
+        const double en = (i > l) ? e[i - 1] : 0.0, ln = (i > l) ? lam[i - 1] : 0.0;
+        const double f = sn * ei, b2 = cs * ei;
+        const double r2 = f * f + g * g;
+        if (r2 == 0.0) {
+          if (lane == 0) { e[i + 1] = 0.0; lam[i + 1] = lam_up - p; e[mm] = 0.0; }
+          under = true;
+          break;
+        }
+        // 1/sqrt(r2): hardware estimate, two Newton steps (quadratic convergence from
+        // the estimate's ~2^-26 relative error to rounding level)
+        double ir = __builtin_amdgcn_rsq(r2);
+        ir = fma(ir, fma(-0.5 * r2 * ir, ir, 0.5), ir);
+        ir = fma(ir, fma(-0.5 * r2 * ir, ir, 0.5), ir);
+        const double rr = r2 * ir;
+        sn = f * ir;
+        cs = g * ir;
+        g = lam_up - p;
+        r = (li - g) * sn + 2.0 * cs * b2;
+        p = sn * r;
+        if (lane == 0) {
+          e[i + 1] = rr;
+          lam[i + 1] = g + p;
+          cb[cnt] = cs;
+          sb[cnt] = sn;
+        }
+        g = cs * r - b2;
+        ++cnt;
+        lam_up = li;
+        ei = en;
+        li = ln;
+      }
+      if (!under && lane == 0) {
+        lam[l] -= p;
+        e[l] = g;
+        e[mm] = 0.0;
+      }
+      break;
+    }
+    if (lane == 0) {
+      nrot[b] = cnt;      // -1: converged
+      top[b] = tp;
+    }
+  };
+  if (scalar) produce(0);
+  __syncthreads();
+  for (int t = 0;; ++t) {
+    const int b = t & 1;
+    const int cnt = nrot[b];
+    if (cnt < 0) break;
+    if (scalar) {
+      produce(b ^ 1);
+    } else if (tid < m) {
+      // rotate row tid of Z: columns (i, i+1) for i = top, top-1, ..., top-cnt+1
+      const int k = tid, tp = top[b];
+      const double* cb = b ? v : rc;
+      const double* sb = b ? pw : rs;
+      double zup = Z[(long)(tp + 1) * ldz + k];
+      // the column entries are loaded eight at a time ahead of their rotations
+      for (int q0 = 0; q0 < cnt; q0 += 8) {
+        double zi[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) zi[u] = (q0 + u < cnt) ? Z[(long)(tp - q0 - u) * ldz + k] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (q0 + u < cnt) {
+            const int i = tp - q0 - u;
+            const double c = cb[q0 + u], sn = sb[q0 + u];
+            Z[(long)(i + 1) * ldz + k] = sn * zi[u] + c * zup;
+            zup = c * zi[u] - sn * zup;
+          }
+        }
+      }
+      Z[(long)(tp - cnt + 1) * ldz + k] = zup;
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < m; i += blockDim.x) lam[i] *= qscale;
+  __syncthreads();
+}
+
 // Column norms of X and the permutation sorting them in decreasing order
 // (ties by index). sig[j] = |x_j|, ord[pos] = j.
 __device__ void sorted_norms(const double* X, int m, int ldx, int n, double* sig, int* ord) {
@@ -291,6 +555,18 @@ __device__ void sorted_norms(const double* X, int m, int ldx, int n, double* sig
     int pos = 0;
     const double s = sig[j];
     for (int i = 0; i < n; ++i) pos += (sig[i] > s) || (sig[i] == s && i < j);
+    ord[pos] = j;
+  }
+  __syncthreads();
+}
+
+// Permutation sorting v[0..n) in decreasing order (ties by index): ord[pos] = j.
+__device__ void rank_desc(const double* v, int n, int* ord) {
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    int pos = 0;
+    const double s = v[j];
+    for (int i = 0; i < n; ++i) pos += (v[i] > s) || (v[i] == s && i < j);
     ord[pos] = j;
   }
   __syncthreads();

@@ -273,20 +273,23 @@ __global__ void __launch_bounds__(256) k_zip_gram(Batch b, Geo g, WsLayout wl) {
 }
 
 // Truncated eigen-decomposition of G (= left singular vectors of Theta): one
-// workgroup per chain. Writes U (first r eigenvectors, decreasing eigenvalue)
-// as core k of y and sets y.bond[k+1] = r.
+// workgroup per chain, Householder tridiagonalisation + implicit QL (sym_eig).
+// Writes U (first r eigenvectors, decreasing eigenvalue) as core k of y and sets
+// y.bond[k+1] = r.
 __global__ void __launch_bounds__(FACT_THREADS) k_zip_factor(Batch b, Geo g, WsLayout wl) {
   extern __shared__ double smem[];
   __shared__ double sig[MAXN];
   __shared__ int ord[MAXN];
-  __shared__ int flag, rank;
+  __shared__ int rank;
   if (blockIdx.x >= b.n) return;
   Chain& c = b.c[blockIdx.x];
   const int k = g.k;
   const int m = 2 * c.yb[k];
   const int ldg = 2 * g.capy;
-  const bool in_lds = (size_t)m * m * sizeof(double) <= (size_t)g.lds;
+  const bool in_lds = ((size_t)m * m + 6 * (size_t)m) * sizeof(double) <= (size_t)g.lds;
   double* G = in_lds ? smem : (c.ws + wl.gpart);
+  double* work = in_lds ? smem + (size_t)m * m : smem;
+  double* Z = c.ws + wl.gpart + (size_t)wl.splits * ldg * ldg;   // slot after the partial products
   const int ld = in_lds ? m : ldg;
   // G is symmetric: column j is read from row j of the partial products, so in
   // the global-memory path each thread reads and writes the same element.
@@ -297,8 +300,13 @@ __global__ void __launch_bounds__(FACT_THREADS) k_zip_factor(Batch b, Geo g, WsL
     G[(long)j * ld + i] = s;
   }
   __syncthreads();
-  jacobi_cols(G, m, ld, m, nullptr, 0, &flag, g.cnt);
-  sorted_norms(G, m, ld, m, sig, ord);
+  sym_eig(G, m, ld, Z, m, sig, work);
+  if (g.cnt && threadIdx.x == 0) {
+    // algorithmic work: tridiagonalisation and accumulation of its factor, 8/3 m^3
+    atomicAdd(g.cnt, (8.0 / 3.0) * (double)m * m * m);
+    atomicAdd(g.cnt + 1, 16.0 * (double)m * m);
+  }
+  rank_desc(sig, m, ord);
   if (threadIdx.x == 0) {
     const double lam0 = sig[ord[0]];
     const double tau = 0.01 * g.tol / sqrt((double)(g.L > 1 ? g.L - 1 : 1));
@@ -309,7 +317,7 @@ __global__ void __launch_bounds__(FACT_THREADS) k_zip_factor(Batch b, Geo g, WsL
     if (r > cap) r = cap;
     if (r < 1) r = 1;
     double disc = 0;
-    for (int q = r; q < m; ++q) disc += sig[ord[q]];
+    for (int q = r; q < m; ++q) disc += fmax(sig[ord[q]], 0.0);
     c.ws[wl.scal + SC_TRUNC2] += disc;
     rank = r;
     c.yb[k + 1] = r;
@@ -320,13 +328,7 @@ __global__ void __launch_bounds__(FACT_THREADS) k_zip_factor(Batch b, Geo g, WsL
   const int S = g.capy * 2 * g.capy;
   for (int e = threadIdx.x; e < S; e += blockDim.x) {
     const int row = e / g.capy, n = e % g.capy;     // row = a' * 2 + r'
-    double v = 0.0;
-    if (row < m && n < r) {
-      const int j = ord[n];
-      const double lam = sig[j];
-      v = lam > 0 ? G[(long)j * ld + row] / lam : 0.0;
-    }
-    Y[e] = v;
+    Y[e] = (row < m && n < r) ? Z[(long)ord[n] * m + row] : 0.0;
   }
 }
 
