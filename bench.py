@@ -239,11 +239,13 @@ def run_path(Q, F, ctx, ops, U0, V0, P0, opts, warmup, steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=10, help="cores per axis (grid 2^n x 2^n)")
     ap.add_argument("--chi", type=int, default=64)
     ap.add_argument("--pois-tol", type=float, default=1e-6, help="pressure tolerance of the fast path")
+    ap.add_argument("--local-tol", type=float, default=1e-2,
+                    help="local CG stop of the solves: reduction of each local residual")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-lowp", action="store_true")
@@ -286,7 +288,7 @@ def main():
     P0 = Q.MPS.from_cores(random_mps_cores(L, chi, seed=0), chi)
 
     def so(tol, sweeps):
-        return Q.solve_opts(tol=tol, max_sweeps=sweeps, max_local_iters=80, local_tol=1e-2, dtype="f64")
+        return Q.solve_opts(tol=tol, max_sweeps=sweeps, max_local_iters=80, local_tol=args.local_tol, dtype="f64")
 
     fast = F.step_opts(dt, tol=1e-8, chi=chi, dtype="f64", product="f64", helm=so(1e-8, 4), pois=so(args.pois_tol, 8))
     plain = F.step_opts(dt, tol=1e-8, chi=chi, dtype="f64", product="f64", helm=so(1e-9, 4), pois=so(1e-9, 8))

@@ -110,6 +110,22 @@ def test_apply_fused_contraction_exact(Q, ctx, cap):
         assert right_orthonormal_error(Y[i].cores()) < 1e-10
 
 
+def test_apply_exact_large_gram(Q, ctx):
+    """L = 16, input bond 64, MPO bond 2: the exact product has bonds up to 128 and
+    fits the output capacity, so the zip-up Gram matrices reach 256 x 256 (the
+    eigen-decomposition with the matrix in global memory) with nothing to truncate."""
+    L, chi, w = 16, 64, 2
+    xc = random_mps_cores(L, chi, seed=50)
+    M = random_mpo_cores(L, w, seed=51)
+    x = _rc(Q, ctx, xc, chi)
+    y = Q.MPS(L, 128)
+    Q.apply_mpo(ctx, [Q.MPO.from_cores(M)], [x], [y], tol=0.0, chi=128)
+    ref = R.mpo_apply_dense(M, R.tt_full(xc))
+    assert max(y.bonds()) == 128
+    assert rel(R.tt_full(y.cores()), ref) < 1e-10
+    assert right_orthonormal_error(y.cores()) < 1e-10
+
+
 def test_apply_batched_matches_single(Q, ctx):
     L = 10
     xs = [random_mps_cores(L, 6, seed=10 + i) for i in range(3)]
