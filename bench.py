@@ -95,11 +95,27 @@ def dense(Q, F, m, n):
     return grid.reshape(N, N)
 
 
+def exact_rel_error(Q, ctx, M_cores, x, y):
+    """||y - M x|| / ||M x|| from exact FP64 TT inner products on the GPU:
+    <y, y> - 2 <y, M x> + <x, (M^T M) x>, with M^T M assembled core by core as an MPO
+    of bond w^2 (no dense vectors at L = 24)."""
+    N = []
+    for c in M_cores:                      # c[a][r'][r][b], r' the output index
+        a, _, _, b = c.shape
+        n = np.einsum("aisb,citd->acstbd", c, c).reshape(a * a, 2, 2, b * b)
+        N.append(n)
+    nn = Q.dot_mpo(ctx, [x], [Q.MPO.from_cores(N)], [x])[0]
+    ym = Q.dot_mpo(ctx, [y], [Q.MPO.from_cores(M_cores)], [x])[0]
+    yy = Q.dot(ctx, [y], [y])[0]
+    return float(np.sqrt(max(nn - 2.0 * ym + yy, 0.0) / nn))
+
+
 def sweep(args):
     """Isolated kernel sweep: random MPS (L = 24, cores N(0, 1/chi)) times random MPO
     (bond w, entries N(0, 1)), zip-up apply plus rounding to chi, `trials` chains per
     call. Reports the site contractions in TFLOP/s from the library's work counters and
-    HIP-event brackets, and the whole apply time. In FP64 at slot capacity 64 or 128 both
+    HIP-event brackets, the whole apply time and, for FP64, the truncation error
+    ||y - M x|| / ||M x|| of the first chain from exact inner products. In FP64 at slot capacity 64 or 128 both
     contractions of a site run in one kernel (k_zip_fused, reported under carry_x_core,
     "fused": true); otherwise k_zip_t1 (carry_x_core) and k_zip_t2 (x_mpo_core)."""
     import torch
@@ -134,6 +150,10 @@ def sweep(args):
                 tf = (a["gflop"] + b["gflop"]) / max(tot_ms, 1e-9)
                 rec["contraction"] = {"tflops": round(tf, 3), "frac_of_peak": round(tf / PEAKS[dt], 5)}
                 rec["fused"] = b["launches"] == 0 and a["launches"] > 0
+                if dt == "f64":
+                    # M^T M has bond w^2; the library's MPO bond limit is 512
+                    rec["trunc_rel_err_trial0"] = (exact_rel_error(Q, ctx, random_mpo_cores(L, w, seed=200), xs[0],
+                                                                   ys[0]) if w * w <= 512 else None)
                 if rec["fused"]:
                     # the fused kernel per site: work from the actual bonds (the zip-up's
                     # output bonds are those of y, which the final sweep at tol 0 keeps),
