@@ -141,10 +141,6 @@ __global__ void __launch_bounds__(256) k_zip_fused(Batch b, Geo g, WsLayout wl) 
   // of loads in flight ahead of the MFMAs
   const gcdp X = as_global(c.x) + (long)k * F::CAP * 2 * F::CAP;
   const int col0 = wave * 16 * NB + li;
-  // column c' of a 16-column block at or beyond the bond x_{k+1} only meets the zero
-  // padding of X_k: such blocks keep zero accumulators and skip loads and MFMAs
-  // (the right end of a chain, where x_{k+1} << capacity)
-  const int cb0 = (wave & 1) * 16 * NB;
   v4d acc[MB][NB];
 #pragma unroll
   for (int u = 0; u < MB; ++u)
@@ -156,8 +152,7 @@ __global__ void __launch_bounds__(256) k_zip_fused(Batch b, Geo g, WsLayout wl) 
     for (int st = 0; st < 4; ++st) {
       const int kk = k0 + 4 * st + lk;
 #pragma unroll
-      for (int v = 0; v < NB; ++v)
-        bq[buf][st][v] = (kk < K1 && cb0 + 16 * v < xb1) ? X[(long)kk * 2 * F::CAP + col0 + 16 * v] : 0.0;
+      for (int v = 0; v < NB; ++v) bq[buf][st][v] = (kk < K1) ? X[(long)kk * 2 * F::CAP + col0 + 16 * v] : 0.0;
     }
   };
   auto mma = [&](int buf, int k0) {
@@ -169,11 +164,10 @@ __global__ void __launch_bounds__(256) k_zip_fused(Batch b, Geo g, WsLayout wl) 
 #pragma unroll
         for (int u = 0; u < MB; ++u) a[u] = As[(kk + lk) * F::LDT + 16 * u + li];
 #pragma unroll
-        for (int v = 0; v < NB; ++v)
-          if (cb0 + 16 * v < xb1)
+        for (int u = 0; u < MB; ++u)
 #pragma unroll
-            for (int u = 0; u < MB; ++u)
-              acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bq[buf][st][v], acc[u][v], 0, 0, 0);
+          for (int v = 0; v < NB; ++v)
+            acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bq[buf][st][v], acc[u][v], 0, 0, 0);
       }
     }
   };
@@ -229,11 +223,10 @@ __global__ void __launch_bounds__(256) k_zip_fused(Batch b, Geo g, WsLayout wl) 
 #pragma unroll
       for (int v = 0; v < NB2; ++v) bb[v] = T1[(kk >> 1) * F::LD + (kk & 1) * F::S1 + n0 + 16 * v + li];
 #pragma unroll
-      for (int v = 0; v < NB2; ++v)
-        if (n0 + 16 * v < xb1)      // columns beyond x_{k+1}: zero (padding)
+      for (int u = 0; u < MB2; ++u)
 #pragma unroll
-          for (int u = 0; u < MB2; ++u)
-            acc2[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[st % AH][u], bb[v], acc2[u][v], 0, 0, 0);
+        for (int v = 0; v < NB2; ++v)
+          acc2[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[st % AH][u], bb[v], acc2[u][v], 0, 0, 0);
       if (st + AH < KS2) load_a2(st % AH, st + AH);
     }
   }
