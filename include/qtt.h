@@ -184,8 +184,9 @@ int qtt_fit(qtt_ctx* ctx, int n, int nterms, const qtt_term* terms, qtt_mps* y, 
  * when every problem's sweep residual is <= tol, at max_sweeps, or when no
  * problem improved its best sweep residual by 10% (after two sweeps). info
  * (HOST, n entries, may be NULL) receives sweeps, CG iterations and the sweep
- * residuals. Returns QTT_ENOTCONVERGED if some problem ended above tol (x then
- * holds its last iterate). */
+ * residuals. A problem with b = 0 gets x = 0 (residual 0). Returns
+ * QTT_ENOTCONVERGED if some problem ended above tol (x then holds its last
+ * iterate), QTT_ENUMERIC if b or a residual is not finite. */
 int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qtt_mps* b, qtt_mps* x,
                       const qtt_solve_opts* opts, qtt_solve_info* info, void* stream);
 

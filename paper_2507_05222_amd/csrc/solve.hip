@@ -798,6 +798,15 @@ extern "C" int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qt
       res[i] = best[i] = INFINITY;
       if (info) { info[i0 + i].residual0 = NAN; info[i0 + i].residual = NAN; info[i0 + i].sweeps = 0; }
     }
+    // b = 0: the solution is the zero train. Its local problems have b_eff = 0 and stop
+    // at once, so x is zeroed here (a zero core keeps the train zero through the gauge
+    // moves, which pass R = 0 on to the neighbour).
+    {
+      ZeroList z{0, (long)L * cx * 2 * cx, {}};
+      for (int i = 0; i < S.sb.n; ++i)
+        if (bb[i] == 0.0) z.p[z.n++] = S.sb.c[i].x;
+      zero_list(z, s);
+    }
     double* pmax = pinned(ctx, 8 * (size_t)n, &rc);
     if (rc) return rc;
     S.flags = pmax + GB;
@@ -850,7 +859,7 @@ extern "C" int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qt
     if (hipStreamSynchronize(s) != hipSuccess) return set_error(ctx, QTT_EHIP, "solve: stream sync failed");
     for (int i = 0; i < S.sb.n; ++i) {
       if (info) info[i0 + i].local_iters = (int)pin[i];
-      if (!std::isfinite(res[i])) status = QTT_ENUMERIC;
+      if (!std::isfinite(res[i]) || !std::isfinite(bb[i])) status = QTT_ENUMERIC;
       else if (res[i] > opts->tol && status == QTT_OK) status = QTT_ENOTCONVERGED;
     }
   }
