@@ -180,6 +180,67 @@ def sweep(args):
             torch.cuda.empty_cache()
 
 
+def shedding(args):
+    """Transient cylinder (C3: 2^10 x 2^10, Re = 200, dt = 2e-3, chi = 64, App. G
+    perturbation) on the fast path, drag and lift every 10 steps, resumable: the TT
+    state, the step count and the force history go to --ckpt-out after every 1000
+    steps and are read from --ckpt-in if given. Once --shedding-steps are done the
+    Strouhal number and lift amplitude (upward zero crossings of C_L, last half of
+    the run) are printed as one JSON line."""
+    import torch
+    from paper_2507_05222_amd import diag as D, flow as F, qtt as Q
+    from qtt_inputs import random_mps_cores
+    n, chi, Re, dt, A0 = 10, 64, 200.0, 2e-3, 1e-2
+    L = 2 * n
+    ctx = Q.Context(0)
+    ops = F.FlowOps(n, 20.0, Re, dt)
+    so = lambda tol, sw: Q.solve_opts(tol=tol, max_sweeps=sw, max_local_iters=80, local_tol=args.local_tol, dtype="f64")
+    opts = F.step_opts(dt, tol=1e-8, chi=chi, dtype="f64", product="f64", helm=so(1e-8, 4), pois=so(args.pois_tol, 8))
+    st = F.FlowState(Q.MPS(L, chi), Q.MPS(L, chi), Q.MPS(L, chi))
+    if args.ckpt_in and os.path.exists(args.ckpt_in):
+        z = np.load(args.ckpt_in, allow_pickle=False)
+        for k in ("u", "v", "p"):
+            getattr(st, k).data.copy_(torch.from_numpy(z[k + "_data"]))
+            getattr(st, k).bond.copy_(torch.from_numpy(z[k + "_bond"]))
+        done, hist = int(z["step"]), [tuple(r) for r in z["hist"]]
+    else:
+        u0, v0 = initial_fields(n, A0)
+        for k, f in (("u", u0), ("v", v0)):
+            getattr(st, k).copy_(Q.tt_svd_host(F.grid_to_qtt_order(f), L, 1e-14, chi, chi))
+        st.p.copy_(Q.MPS.from_cores(random_mps_cores(L, chi, seed=0), chi))
+        done, hist = 0, []
+
+    def save():
+        if args.ckpt_out:
+            np.savez(args.ckpt_out, step=done, hist=np.array(hist if hist else np.zeros((0, 3))),
+                     **{k + "_data": getattr(st, k).data.cpu().numpy() for k in ("u", "v", "p")},
+                     **{k + "_bond": getattr(st, k).bond.cpu().numpy() for k in ("u", "v", "p")})
+
+    total = args.shedding_steps
+    end = min(total, done + args.steps_per_call)
+    t0 = time.perf_counter()
+    s0 = done
+    while done < end:
+        F.fractional_step(ctx, ops, st, opts)
+        done += 1
+        if done % 10 == 0:
+            cd, cl = D.forces(ctx, ops.cyl, st.u, st.v, st.p)
+            hist.append((done, cd, cl))
+        if done % 1000 == 0 or done == end:
+            torch.cuda.synchronize()
+            save()
+            print(f"[bench] shedding step {done}/{total} t {done * dt:.2f} C_D {hist[-1][1]:.5f} C_L {hist[-1][2]:.3e} "
+                  f"{(done - s0) / (time.perf_counter() - t0):.2f} steps/s", file=sys.stderr, flush=True)
+    out = {"workload": f"transient cylinder Re={Re:g}, O-grid 2^{n}x2^{n}, chi={chi}, dt={dt:g}, A0={A0:g}",
+           "steps_done": done, "steps_total": total,
+           "steps_per_s_this_call": round((done - s0) / (time.perf_counter() - t0), 3)}
+    if done >= total and hist:
+        h = np.array(hist)
+        St, amp = D.strouhal(h[:, 0] * dt, h[:, 2])
+        out.update({"St": St, "lift_amplitude": amp, "C_D_mean_last_half": float(h[len(h) // 2:, 1].mean())})
+    print(json.dumps(out), flush=True)
+
+
 def steady(args):
     """Steady cylinder flow, Re = 40, O-grid 2^8 x 2^8 (16 cores), chi = 32, dt = 5e-3:
     the same run with FP64 and with FP32-MFMA contractions (fits and Hadamard
@@ -279,6 +340,12 @@ def main():
     ap.add_argument("--steady", action="store_true",
                     help="steady cylinder Re=40 on 2^8 x 2^8, chi 32: FP64 vs FP32-MFMA contractions, forces vs the oracle")
     ap.add_argument("--steady-steps", type=int, default=2000)
+    ap.add_argument("--shedding", action="store_true",
+                    help="transient cylinder Re=200 (C3) on the fast path with forces every 10 steps, resumable")
+    ap.add_argument("--shedding-steps", type=int, default=20000)
+    ap.add_argument("--steps-per-call", type=int, default=20000)
+    ap.add_argument("--ckpt-in", default=None)
+    ap.add_argument("--ckpt-out", default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -289,6 +356,9 @@ def main():
         return
     if args.steady:
         steady(args)
+        return
+    if args.shedding:
+        shedding(args)
         return
 
     import torch
