@@ -229,6 +229,7 @@ def shedding(args):
         if done % 1000 == 0 or done == end:
             torch.cuda.synchronize()
             save()
+        if done % 250 == 0 or done == end:
             print(f"[bench] shedding step {done}/{total} t {done * dt:.2f} C_D {hist[-1][1]:.5f} C_L {hist[-1][2]:.3e} "
                   f"{(done - s0) / (time.perf_counter() - t0):.2f} steps/s", file=sys.stderr, flush=True)
     out = {"workload": f"transient cylinder Re={Re:g}, O-grid 2^{n}x2^{n}, chi={chi}, dt={dt:g}, A0={A0:g}",
