@@ -349,7 +349,7 @@ def main():
     ap.add_argument("--ckpt-out", default=None)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this library is measured on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     if args.sweep:

@@ -1,6 +1,6 @@
 """Diagnostics of Sec. 4 and App. F: weighted L2 errors, forces, Strouhal number.
 
-Readings (listed in the design doc):
+Readings where the paper leaves a choice open:
 * the L2 weight is |J| (J < 0 on this grid orientation), Eq. (error);
 * force on the body F = sum_j tau(x_j) n_j R 2 pi d_xi with n = (cos t, sin t)
   pointing into the fluid, R = D/2 (App. F); C = 2F (Eq. liftdrag, rho = U = D = 1);

@@ -14,7 +14,7 @@ tends to this one. This module is that classical implementation, in FP64:
 * the Chorin fractional step, Eqs. (intermediate_vel_eq) and (Poisson) and the
   projection that follows them (Sec. 3.3), with the J-weighted Poisson system (Sec. 3.3).
 
-Readings (listed in DESIGN.md): wall pressure ghost value p_{-1,j} = p_{0,j};
+Readings where the paper leaves a choice open: wall pressure ghost value p_{-1,j} = p_{0,j};
 the J-weight uses |J| (J < 0 for this orientation); the viscous term is implicit
 and convection explicit, as in Eq. (intermediate_vel_eq).
 """

@@ -7,7 +7,7 @@ Follows App. E (Eq. mesh) for the points and App. A for the metrics:
 Metric derivatives are second-order central differences in the computational
 coordinates (App. A), periodic in xi.
 
-Reading (listed in the design doc): metric terms at the two boundary rows need one
+Reading where the paper leaves a choice open: metric terms at the two boundary rows need one
 more row of points on each side; those rows are taken from the same mesh formula
 evaluated at i = -2 and i = N_eta + 1.
 """

@@ -101,7 +101,8 @@ def bond_cap_profile(L, chi, d=2):
 
 
 # ----------------------------------------------------------------------------
-# TT-SVD (Sec. 2, successive SVDs; truncation rule read as in the design doc)
+# TT-SVD (Sec. 2, successive SVDs; truncation: the smallest rank whose discarded
+# singular values have Frobenius norm <= delta, capped at chi_max)
 # ----------------------------------------------------------------------------
 
 def choose_rank(s, delta, chi_max):
