@@ -321,8 +321,8 @@ def run_path(Q, F, ctx, ops, U0, V0, P0, opts, warmup, steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=10, help="cores per axis (grid 2^n x 2^n)")
     ap.add_argument("--chi", type=int, default=64)
     ap.add_argument("--pois-tol", type=float, default=1e-6, help="pressure tolerance of the fast path")
