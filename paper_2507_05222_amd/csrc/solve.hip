@@ -654,6 +654,7 @@ struct Solver {
   // products only have to reduce the error of each correction, while the residual
   // that decides convergence is always exact to FP64.
   double* flags = nullptr;   // host pinned, GB entries
+  bool flag_copy_failed = false;   // a failed flag read stops the enqueuing; the sweep reports it
   void local_solve(int k, int mmode) {
     SGeo gg = g;
     gg.k = k;
@@ -682,9 +683,15 @@ struct Solver {
       it += m;
       chunk = std::min(2 * chunk, 64);
       if (it >= maxit || !flags) break;
+      bool ok = true;
       for (int i = 0; i < sb.n; ++i)
-        (void)hipMemcpyAsync(flags + i, sb.c[i].ws + l.sc + S_DONE, sizeof(double), hipMemcpyDeviceToHost, s);
-      (void)hipStreamSynchronize(s);
+        ok = ok && hipMemcpyAsync(flags + i, sb.c[i].ws + l.sc + S_DONE, sizeof(double), hipMemcpyDeviceToHost,
+                                  s) == hipSuccess;
+      ok = ok && hipStreamSynchronize(s) == hipSuccess;
+      if (!ok) {
+        flag_copy_failed = true;
+        break;
+      }
       bool all = true;
       for (int i = 0; i < sb.n; ++i) all = all && flags[i] != 0.0;
       if (all) break;
@@ -831,6 +838,7 @@ extern "C" int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qt
         S.local_solve(k - 1, S.mode);
       }
       ++sweeps;
+      if (S.flag_copy_failed) return set_error(ctx, QTT_EHIP, "solve: copy of the CG flags failed");
       for (int i = 0; i < S.sb.n; ++i)
         if (hipMemcpyAsync(pmax + i, S.sb.c[i].ws + lay.sc + S_PMAX, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
           return set_error(ctx, QTT_EHIP, "solve: copy of the residual failed");
