@@ -455,6 +455,7 @@ def main():
                 "kernel": "k_gemm_jobs<0, 32|64> (batched FP64 MFMA site/environment contractions, both tile sizes)",
                 "avg_launch_us": round(1e3 * kt["ms"] / kt["launches"], 3), "launches": kt["launches"],
                 "timing": "HIP-event bracket per launch (includes its dispatch: an upper bound)",
+                "idle_bracket_us": round(1e3 * kt["idle_bracket_ms"], 3),
                 "kernel_trace_avg_us": None if prof is None else prof["trace_avg_us"],
                 "flops_per_launch": round(kt["flops"] / kt["launches"], 1),
                 "bytes_per_launch": round(kt["bytes"] / kt["launches"], 1)}
