@@ -114,10 +114,8 @@ def lib():
         L.qtt_dot.argtypes = [vp, i32, p(CMps), p(CMps), p(ctypes.c_double), vp]
         L.qtt_dot_mpo.argtypes = [vp, i32, p(CMps), p(CMpo), p(CMps), p(ctypes.c_double), vp]
         L.qtt_apply_local.argtypes = [vp, i32, p(CMpo), p(CMps), p(CMps), vp]
-        if hasattr(L, "qtt_poisson_solve"):
-            L.qtt_poisson_solve.argtypes = [vp, i32, p(CMpo), p(CMps), p(CMps), p(CSolveOpts), p(CSolveInfo), vp]
-        if hasattr(L, "qtt_fractional_step"):
-            L.qtt_fractional_step.argtypes = [vp, p(CFlowOps), p(CFlowState), p(CStepOpts), p(CStepInfo), vp]
+        L.qtt_poisson_solve.argtypes = [vp, i32, p(CMpo), p(CMps), p(CMps), p(CSolveOpts), p(CSolveInfo), vp]
+        L.qtt_fractional_step.argtypes = [vp, p(CFlowOps), p(CFlowState), p(CStepOpts), p(CStepInfo), vp]
         L.qtt_fit.argtypes = [vp, i32, i32, p(CTerm), p(CMps), i32, i32, i32, i32, vp]
         L.qtt_timer_start.argtypes = [vp, i32]
         L.qtt_timer_read.argtypes = [vp, p(ctypes.c_int64), p(ctypes.c_double), p(ctypes.c_double),
