@@ -1,6 +1,7 @@
-"""The library's wall-force computation (qtt_forces_host, host FP64) against the
-oracle's (oracle/diag.py, pinned by closed forms) on the same dense fields: an FD
-step of the rotating cylinder on the 2^5 x 2^5 grid. No GPU."""
+"""Host read-outs of the library against the oracle's (oracle/diag.py, pinned by
+closed forms): the wall forces (qtt_forces_host, host FP64) on the same dense
+fields, an FD step of the rotating cylinder on the 2^5 x 2^5 grid, and the
+Strouhal number and lift amplitude of a lift history. No GPU."""
 import ctypes
 
 import numpy as np
@@ -30,3 +31,20 @@ def test_forces_host_matches_oracle():
     assert Q.lib().qtt_forces_host(ctypes.byref(cyl), rows.ctypes.data, ctypes.byref(cd), ctypes.byref(cl)) == 0
     assert abs(cd.value - cd_o) <= 1e-12 * abs(cd_o) and abs(cl.value - cl_o) <= 1e-12 * max(abs(cl_o), 1e-3), \
         (cd.value, cd_o, cl.value, cl_o)
+
+
+def test_strouhal_matches_oracle():
+    """The binding's Strouhal read-out against the oracle's on a lift history shaped
+    like the transient cylinder's (growing, then saturating oscillation, sampled
+    every 10 steps of dt = 2e-3), and against the closed form of a pure sinusoid."""
+    from oracle import diag
+    from paper_2507_05222_amd import diag as D
+    t = 2e-3 * 10 * np.arange(1, 2001)
+    env = 0.6 * (1.0 - np.exp(-t / 12.0))
+    cl = 0.02 + env * np.sin(2 * np.pi * 0.192 * t + 0.3)
+    st_o, amp_o = diag.strouhal(t, cl, min_periods=2)
+    st, amp = D.strouhal(t, cl)
+    assert abs(st - st_o) <= 1e-12 * st_o and abs(amp - amp_o) <= 1e-12 * amp_o
+    assert abs(st - 0.192) < 2e-3
+    st, amp = D.strouhal(t, 0.4 * np.sin(2 * np.pi * 0.2 * t))
+    assert abs(st - 0.2) < 1e-5 and abs(amp - 0.4) < 1e-3
