@@ -212,6 +212,9 @@ typedef struct {
 
 typedef struct {
   qtt_mps u, v, p;          /* current fields (right-canonical)                  */
+  uint64_t id;              /* caller-chosen identity of this state, unique among the
+                               states alive on a context; 0 = none (every step starts
+                               its fits cold)                                       */
 } qtt_flow_state;
 
 /* Learned warm start of the pressure solve (see the qtt_ws_* calls below). */

@@ -41,6 +41,7 @@ struct qtt_ctx {
   // the step's temporaries hold its intermediate fields, the warm start of the
   // next step of the same state only
   const void* step_warm_id[3] = {nullptr, nullptr, nullptr};
+  uint64_t step_warm_gen = 0;   // the caller's state id (0 = none)
   int step_warm_L = 0, step_warm_cap = 0;
 };
 
@@ -240,7 +241,9 @@ int qtt_apply_mpo(qtt_ctx* ctx, int n, const qtt_mpo* M, const qtt_mps* x, qtt_m
       return fail(ctx, QTT_ESHAPE, "apply: problems of one call must share L and capacities");
     if (x[i].data == y[i].data) return fail(ctx, QTT_EINVAL, "apply: x and y alias");
   }
-  if (2 * capy > 2 * 512) return fail(ctx, QTT_ESHAPE, "apply: output cap too large");
+  // the zip-up factorises Gram matrices of order 2 * bond in one workgroup (at most 512)
+  if (std::min(tr->chi_max, capy) > 256)
+    return fail(ctx, QTT_ESHAPE, "apply: min(chi_max, y.cap) = %d exceeds 256", std::min(tr->chi_max, capy));
   HIPCHK(ctx, hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   const int splits = split_for(W * capx);
@@ -507,12 +510,12 @@ const double* identity_mpo(qtt_ctx* ctx, int L, const int** bond, int* rc) {
   *bond = ctx->idb;
   return ctx->idm;
 }
-bool step_warm(qtt_ctx* ctx, const void* const id[3], int L, int cap) {
-  return ctx->step_warm_L == L && ctx->step_warm_cap == cap && ctx->step_warm_id[0] == id[0] &&
-         ctx->step_warm_id[1] == id[1] && ctx->step_warm_id[2] == id[2];
+bool step_warm(qtt_ctx* ctx, uint64_t gen, const void* const id[3], int L, int cap) {
+  return gen != 0 && ctx->step_warm_gen == gen && ctx->step_warm_L == L && ctx->step_warm_cap == cap &&
+         ctx->step_warm_id[0] == id[0] && ctx->step_warm_id[1] == id[1] && ctx->step_warm_id[2] == id[2];
 }
-void set_step_warm(qtt_ctx* ctx, const void* const id[3], int L, int cap) {
-  ctx->step_warm_L = L; ctx->step_warm_cap = cap;
+void set_step_warm(qtt_ctx* ctx, uint64_t gen, const void* const id[3], int L, int cap) {
+  ctx->step_warm_gen = gen; ctx->step_warm_L = L; ctx->step_warm_cap = cap;
   for (int i = 0; i < 3; ++i) ctx->step_warm_id[i] = id[i];
 }
 int lds_of(qtt_ctx* ctx) { return ctx->lds; }

@@ -12,7 +12,7 @@
 // Every linear combination of products is one variational fit (Sec. 2.2,
 // qtt_fit) at the state's bond dimension; the two solves are the variational
 // ALS solver (qtt_poisson_solve). Independent chains run batched. When the
-// previous step on this context advanced the same state (same u, v, p storage),
+// previous step on this context advanced the same state (same id and storage),
 // the fits start from that step's results, otherwise from a random sketch.
 #include <algorithm>
 #include <cmath>
@@ -30,8 +30,8 @@ extern "C" int qtt_ws_forward(qtt_ctx* ctx, const float* params, const float* in
 namespace qtt_solver_detail {
 double* step_pool(qtt_ctx* ctx, size_t doubles, int* rc);
 int set_error(qtt_ctx* ctx, int code, const char* msg);
-bool step_warm(qtt_ctx* ctx, const void* const id[3], int L, int cap);
-void set_step_warm(qtt_ctx* ctx, const void* const id[3], int L, int cap);
+bool step_warm(qtt_ctx* ctx, uint64_t gen, const void* const id[3], int L, int cap);
+void set_step_warm(qtt_ctx* ctx, uint64_t gen, const void* const id[3], int L, int cap);
 }
 
 namespace {
@@ -242,7 +242,7 @@ extern "C" int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_fl
   const int chi = std::min(o->trunc.chi_max, cap);
   // warm fits only when the temporaries come from the previous step of this state
   const void* const sid[3] = {st->u.data, st->v.data, st->p.data};
-  const bool warm = step_warm(ctx, sid, L, cap);
+  const bool warm = step_warm(ctx, st->id, sid, L, cap);
   const int init = warm ? 0 : 1;
   const int sweeps = warm ? std::max(1, o->trunc.fit_sweeps) : std::max(2, o->trunc.fit_sweeps);
   const int mode = o->contract_dt;
@@ -335,6 +335,6 @@ extern "C" int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_fl
     qtt_mps y[2] = {st->u, st->v};
     if ((rc = qtt_fit(ctx, 2, 2, t, y, chi, sweeps, init, mode, stream))) return rc;
   }
-  set_step_warm(ctx, sid, L, cap);
+  set_step_warm(ctx, st->id, sid, L, cap);
   return QTT_OK;
 }

@@ -4,6 +4,7 @@ Marshalling only; all arithmetic runs in libqtt.so."""
 from __future__ import annotations
 
 import ctypes
+import itertools
 
 import numpy as np
 
@@ -39,11 +40,17 @@ class FlowOps:
 
 
 class FlowState:
+    """u, v, p of one flow. Each instance gets its own nonzero id: the library keys
+    the warm start of a step's fits on it, not on storage addresses, which the
+    allocator hands on to later states."""
+    _ids = itertools.count(1)
+
     def __init__(self, u: Q.MPS, v: Q.MPS, p: Q.MPS):
         self.u, self.v, self.p = u, v, p
+        self.id = next(FlowState._ids)
 
     def c(self):
-        return Q.CFlowState(self.u.desc(), self.v.desc(), self.p.desc())
+        return Q.CFlowState(self.u.desc(), self.v.desc(), self.p.desc(), self.id)
 
 
 def step_opts(dt, tol=1e-8, chi=64, dtype="f64", helm=None, pois=None, fit=2, product=None, warm=None,

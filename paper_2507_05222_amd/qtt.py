@@ -68,7 +68,7 @@ class CFlowOps(ctypes.Structure):
 
 
 class CFlowState(ctypes.Structure):
-    _fields_ = [("u", CMps), ("v", CMps), ("p", CMps)]
+    _fields_ = [("u", CMps), ("v", CMps), ("p", CMps), ("id", ctypes.c_uint64)]
 
 
 class CWsModel(ctypes.Structure):

@@ -133,3 +133,8 @@ def test_malformed_calls_return_errors(Q, ctx):
     big = Q.MPS(8, 300)
     with pytest.raises(Q.QttError, match="ESHAPE"):
         Q.poisson_solve(ctx, [M8], [big], [Q.MPS(8, 300)], Q.solve_opts())
+    # the zip-up factorises Gram matrices of order 2 * bond in one workgroup: an
+    # output bond above 256 is refused before any launch
+    y512 = Q.MPS(8, 512)
+    with pytest.raises(Q.QttError, match="ESHAPE"):
+        Q.apply_mpo(ctx, [M8], [x8], [y512], tol=0.0, chi=512)

@@ -58,3 +58,41 @@ def test_step_warm_start_is_per_state():
         x = R.tt_full(getattr(b, name).cores())
         y = R.tt_full(getattr(b_ref, name).cores())
         assert np.linalg.norm(x - y) <= 1e-9 * np.linalg.norm(y), name
+
+
+def test_step_warm_start_not_taken_from_a_freed_state():
+    """A state freed after its step and a new state of the same shape: the allocator
+    may hand the new state the old storage, but its id differs, so its first step
+    starts cold and equals the same step on a fresh context."""
+    import gc
+    import numpy as np
+    import torch
+    from paper_2507_05222_amd import flow as F, qtt as Q
+    from oracle import qttref as R
+    from qtt_inputs import noise_fields, random_mps_cores
+    n, cap, L = 5, 8, 10
+    perm = R.grid_perm(n, n)
+    ops = F.FlowOps(n, 20.0, 100.0, 1e-3)
+
+    def state(seed):
+        nz = noise_fields(n, n, 1e-2, seed=seed)
+        u = Q.tt_svd_host((1.0 + nz[0]).ravel()[perm], L, 0.0, cap, cap)
+        v = Q.tt_svd_host(nz[1].ravel()[perm], L, 0.0, cap, cap)
+        p = Q.MPS.from_cores(random_mps_cores(L, cap, seed=0), cap)
+        return F.FlowState(u, v, p)
+
+    opts = F.step_opts(1e-3, tol=1e-12, chi=cap, dtype="f64")
+    shared = Q.Context(0)
+    a = state(1)
+    F.fractional_step(shared, ops, a, opts)
+    del a
+    gc.collect()
+    b = state(2)
+    F.fractional_step(shared, ops, b, opts)
+    b_ref = state(2)
+    F.fractional_step(Q.Context(0), ops, b_ref, opts)
+    torch.cuda.synchronize()
+    for name in ("u", "v", "p"):
+        x = R.tt_full(getattr(b, name).cores())
+        y = R.tt_full(getattr(b_ref, name).cores())
+        assert np.linalg.norm(x - y) <= 1e-9 * np.linalg.norm(y), name
