@@ -132,6 +132,16 @@ const char* qtt_last_error(const qtt_ctx* ctx);
 int qtt_apply_mpo(qtt_ctx* ctx, int n, const qtt_mpo* M, const qtt_mps* x, qtt_mps* y,
                   const qtt_trunc* tr, int contract_dt, void* stream);
 
+/* TT-SVD of a dense vector into a device MPS (Sec. 2, Eq. simpleMPS; App. D for the
+ * digit order): `dense` is a HOST array of 2^L doubles (1 <= L <= 26), entry
+ * sum_k r_k 2^(L-1-k) at index r_0 .. r_{L-1} (core 0 the most significant digit).
+ * Successive truncated SVDs from the left on the host (FP64, the qtt_trunc rule
+ * with chi_max capped at out->cap), the cores are then copied into out's slots
+ * (entries outside the bonds zero) and out->bond is set; the call synchronises
+ * the stream. QTT_ENUMERIC if the input holds NaN or Inf. For encoding initial
+ * fields and coarse predictions: the time step itself never decompresses. */
+int qtt_from_dense(qtt_ctx* ctx, const double* dense, int32_t L, const qtt_trunc* tr, qtt_mps* out, void* stream);
+
 /* In-place TT-rounding (Sec. 2: regular truncation): left-to-right Householder QR
  * sweep, then right-to-left truncated SVD (one-sided Jacobi) sweep, FP64.
  * The result is right-canonical. */
@@ -283,7 +293,9 @@ int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_flow_state* s
  * right-to-left Jacobi SVD sites, 5 Householder QR/LQ moves, 6 environment /
  * local-matvec / projection GEMMs on FP64 MFMA, 7 local CG updates, 8 the GEMMs of
  * class 6 on FP32 or BF16 MFMA, 9 zip-up product with the MPO core when it is not
- * fused into class 0; -1 stops timing.
+ * fused into class 0, 10 whole local CG solves of qtt_poisson_solve run as one
+ * cooperative launch each (FP64 contractions at slot capacity <= 64: both products
+ * of every iteration counted); -1 stops timing.
  * qtt_timer_read synchronises the device and returns the number of timed
  * launches, the summed duration of their event brackets (ms), the counted work,
  * and, for reference, the mean duration of the same bracket around an empty
@@ -342,6 +354,15 @@ int qtt_read_rows(qtt_ctx* ctx, const qtt_mps* x, int nrows, const int32_t* rows
  * derivatives one-sided second order in eta, central in xi; host FP64. */
 int qtt_forces_host(const qtt_cylinder* cyl, const double* rows, double* cd, double* cl);
 
+/* Strouhal number and lift amplitude of a sampled lift history (Sec. 4.1.2, Eq.
+ * st with D = U = 1; host FP64): over the last `window` (0 < window <= 1) of the n
+ * samples (t[i], cl[i]) (HOST arrays, t increasing), y = cl - mean(cl); upward
+ * crossings y_i < 0 <= y_{i+1} are located by linear interpolation and
+ * St = 1 / (mean spacing of the crossings); amp = (max cl - min cl) / 2 over the
+ * window. St is NaN with fewer than min_crossings (>= 2) crossings. */
+int qtt_strouhal_host(const double* t, const double* cl, int64_t n, double window, int32_t min_crossings,
+                      double* st, double* amp);
+
 /* Host TT-SVD of a dense vector of d^L doubles (App. D; same truncation rule as
  * qtt_trunc), used to encode initial fields. Writes cores into slots of
  * cap*d*cap doubles (HOST) and bonds to bond_out (HOST int32[L+1]). */
@@ -381,6 +402,12 @@ int qtt_ws_mse(qtt_ctx* ctx, const float* out, const float* target, int n, float
  * the 64 x 64 grid (its last L - 12 cores contracted with [1/2, 1/2]): grid
  * (HOST, 4096 doubles) receives [row eta][column xi]. Synchronises the stream. */
 int qtt_ws_coarse(qtt_ctx* ctx, const qtt_mps* x, double* grid, void* stream);
+/* Network input of one right-hand side (the rule used by qtt_fractional_step and by
+ * the training pairs alike): coarse_b (HOST, 4096 doubles, [eta][xi]) ->
+ * in (HOST, 3 x 4096 floats) = (b / rms(b), Re / 200, alpha / 2); *rms = rms(b), the
+ * scale of the network's output. QTT_ENUMERIC (in unwritten) if rms(b) is 0 or
+ * not finite. */
+int qtt_ws_input_host(const double* coarse_b, double re, double alpha, float* in, double* rms);
 /* One Adam step (Kingma & Ba, beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected,
  * step >= 1) on QTT_WS_NPARAMS parameters; m and v are the moment buffers. */
 int qtt_ws_adam_step(qtt_ctx* ctx, float* params, const float* grads, float* m, float* v, int step, float lr,

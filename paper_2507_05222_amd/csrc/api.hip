@@ -9,10 +9,12 @@
 #include <vector>
 
 #include "../../include/qtt.h"
+#include "host_linalg.h"
 #include "internal.h"
 
 namespace qtt_solver_detail {
 hipError_t solver_init(int lds);
+int coop_capacity(int device);
 hipError_t fit_init(int lds);
 int fit_sweeps(qtt_ctx* ctx, int n, const qtt_mpo* M, const qtt_mps* x, qtt_mps* y, int sweeps, int mode,
                void* stream);
@@ -21,6 +23,7 @@ int fit_sweeps(qtt_ctx* ctx, int n, const qtt_mpo* M, const qtt_mps* x, qtt_mps*
 struct qtt_ctx {
   int device = 0;
   int lds = 64 * 1024;
+  int coop = 0;                // workgroups of the one-launch local CG resident at once (0: unavailable)
   std::string err;
   double* ws = nullptr;        // chain workspaces (device)
   size_t ws_cap = 0;           // doubles
@@ -204,6 +207,7 @@ int qtt_create(int device, qtt_ctx** out) {
   if (e == hipSuccess) e = qtt_solver_detail::solver_init(ctx->lds);
   if (e == hipSuccess) e = qtt_solver_detail::fit_init(ctx->lds);
   if (e != hipSuccess) { delete ctx; return QTT_EHIP; }
+  ctx->coop = qtt_solver_detail::coop_capacity(device);
   *out = ctx;
   return QTT_OK;
 }
@@ -269,6 +273,35 @@ int qtt_apply_mpo(qtt_ctx* ctx, int n, const qtt_mpo* M, const qtt_mps* x, qtt_m
   if ((rc = launch_status(ctx))) return rc;
   // variational refinement (Sec. 2.2): fitting sweeps at the bonds chosen above
   return qtt_solver_detail::fit_sweeps(ctx, n, M, x, y, tr->fit_sweeps, contract_dt, stream);
+}
+
+int qtt_from_dense(qtt_ctx* ctx, const double* dense, int32_t L, const qtt_trunc* tr, qtt_mps* out, void* stream) {
+  if (!ctx) return QTT_EINVAL;
+  if (!dense || !out || L < 1 || L > 26) return fail(ctx, QTT_EINVAL, "from_dense: bad arguments");
+  int rc = check_trunc(ctx, tr);
+  if (rc) return rc;
+  if ((rc = check_mps(ctx, *out, "from_dense out"))) return rc;
+  if (out->L != L) return fail(ctx, QTT_ESHAPE, "from_dense: out.L = %d, expected %d", out->L, L);
+  const int cap = out->cap;
+  std::vector<double> v(dense, dense + ((size_t)1 << L));
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(ctx, QTT_ENUMERIC, "from_dense: non-finite input");
+  const HostTT T = tt_svd_host(v, L, 2, tr->rel_tol, std::min(tr->chi_max, cap), 0.0);
+  std::vector<double> slots((size_t)L * cap * 2 * cap, 0.0);
+  std::vector<int32_t> bonds(L + 1);
+  for (int k = 0; k <= L; ++k) bonds[k] = T.bl[k];
+  for (int k = 0; k < L; ++k)
+    for (int a = 0; a < T.bl[k]; ++a)
+      for (int s2 = 0; s2 < 2; ++s2)
+        for (int b = 0; b < T.bl[k + 1]; ++b)
+          slots[(size_t)k * cap * 2 * cap + (size_t)a * 2 * cap + s2 * cap + b] =
+              T.cores[k][((size_t)a * 2 + s2) * T.bl[k + 1] + b];
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(ctx, hipMemcpyAsync(out->data, slots.data(), slots.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipMemcpyAsync(out->bond, bonds.data(), bonds.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));   // the host buffers are released on return
+  return QTT_OK;
 }
 
 int qtt_round(qtt_ctx* ctx, int n, qtt_mps* x, const qtt_trunc* tr, void* stream) {
@@ -519,6 +552,7 @@ void set_step_warm(qtt_ctx* ctx, uint64_t gen, const void* const id[3], int L, i
   for (int i = 0; i < 3; ++i) ctx->step_warm_id[i] = id[i];
 }
 int lds_of(qtt_ctx* ctx) { return ctx->lds; }
+int coop_of(qtt_ctx* ctx) { return ctx->coop; }
 double* pinned(qtt_ctx* ctx, size_t doubles, int* rc) {
   *rc = ensure_pinned(ctx, doubles);
   return *rc ? nullptr : ctx->pinned;

@@ -482,3 +482,54 @@ extern "C" int qtt_forces_host(const qtt_cylinder* cyl, const double* rows, doub
   *cl = 2.0 * Fz;
   return QTT_OK;
 }
+
+// Strouhal number and lift amplitude of a lift history (Sec. 4.1.2: interpolated
+// zero crossings of C_L; Eq. st with D = U = 1): over the last `window` of the
+// samples, y = C_L - mean; upward crossings (y_i < 0 <= y_{i+1}) are located by
+// linear interpolation; St = 1 / (mean spacing of the crossings).
+extern "C" int qtt_strouhal_host(const double* t, const double* cl, int64_t n, double window, int32_t min_crossings,
+                                 double* st, double* amp) {
+  if (!t || !cl || !st || !amp || n < 2 || !(window > 0.0 && window <= 1.0) || min_crossings < 2) return QTT_EINVAL;
+  const int64_t n0 = (int64_t)((double)n * (1.0 - window));
+  const int64_t m = n - n0;
+  if (m < 2) return QTT_EINVAL;
+  double mean = 0.0, lo = cl[n0], hi = cl[n0];
+  for (int64_t i = n0; i < n; ++i) {
+    mean += cl[i];
+    lo = std::min(lo, cl[i]);
+    hi = std::max(hi, cl[i]);
+  }
+  mean /= (double)m;
+  *amp = 0.5 * (hi - lo);
+  double first = 0.0, last = 0.0;
+  int64_t count = 0;
+  for (int64_t i = n0; i + 1 < n; ++i) {
+    const double y0 = cl[i] - mean, y1 = cl[i + 1] - mean;
+    if (y0 < 0.0 && y1 >= 0.0) {
+      const double tc = t[i] - y0 * (t[i + 1] - t[i]) / (y1 - y0);
+      if (count == 0) first = tc;
+      last = tc;
+      ++count;
+    }
+  }
+  *st = (count >= min_crossings && last > first) ? (double)(count - 1) / (last - first) : NAN;
+  return QTT_OK;
+}
+
+// Input of the learned warm start's network from the block-averaged right-hand
+// side b (64 x 64, [eta][xi]): channels b / rms(b), Re / 200, alpha / 2 (FP32,
+// NCHW); rms(b) is returned, being the scale of the network's output.
+extern "C" int qtt_ws_input_host(const double* coarse_b, double re, double alpha, float* in, double* rms) {
+  if (!coarse_b || !in || !rms) return QTT_EINVAL;
+  double ms = 0.0;
+  for (int e = 0; e < 4096; ++e) ms += coarse_b[e] * coarse_b[e];
+  const double r = std::sqrt(ms / 4096.0);
+  *rms = r;
+  if (!(r > 0.0) || !std::isfinite(r)) return QTT_ENUMERIC;
+  for (int e = 0; e < 4096; ++e) {
+    in[e] = (float)(coarse_b[e] / r);
+    in[4096 + e] = (float)(re / 200.0);
+    in[8192 + e] = (float)(alpha / 2.0);
+  }
+  return QTT_OK;
+}

@@ -59,7 +59,7 @@ struct FGeo {
 // per-chain workspace: for each term its environments, transposes and scratch
 struct FLay {
   size_t env[MAXT], LA[MAXT], RA[MAXT], Mt[MAXT], Mt2[MAXT], F1[MAXT], F2[MAXT];
-  size_t tmpA, gp, total;
+  size_t tmpA, gp, slab, total;
   static FLay make(int L, int cy, const int* ck, int W, int nt) {
     FLay l;
     size_t o = 0;
@@ -76,6 +76,7 @@ struct FLay {
     }
     l.tmpA = o; o += al(4 * (size_t)cy * cy);
     l.gp = o; o += al(4 * 4 * (size_t)cy * cy);
+    l.slab = o; o += al((size_t)nt * KSPLIT_MAX * 2 * cy * cy);   // split products of the projection
     l.total = o;
     return l;
   }
@@ -232,13 +233,14 @@ struct Fitter {
     j.alpha = 1.0; j.beta = 0.0;
   }
   // launch a list of jobs in groups of GB (one launch per group)
-  void run(std::vector<GemmJob>& jobs, int maxb, int maxM, int maxN, int m, int ksplit = 1) {
+  void run(std::vector<GemmJob>& jobs, int maxb, int maxM, int maxN, int m, int ksplit = 1, long slab = 0) {
     for (size_t i0 = 0; i0 < jobs.size(); i0 += GB) {
       GemmBatch gb;
       std::memset(&gb, 0, sizeof(gb));
       gb.n = (int)std::min<size_t>(GB, jobs.size() - i0);
       gb.maxb = maxb;
       gb.ksplit = ksplit;
+      gb.slab = slab;
       for (int i = 0; i < gb.n; ++i) gb.j[i] = jobs[i0 + i];
       run_jobs(gb, maxM, maxN, m, s);
     }
@@ -272,17 +274,16 @@ struct Fitter {
     run(b, g.cy, 2 * g.W, maxck, mode);
   }
 
-  // Y_k = sum_t c_t F2_t . RA^t_{k+1}: Y_k is zeroed, then every (chain, term) product,
-  // split over K, adds into it with atomic adds.
+  // Y_k = sum_t c_t F2_t . RA^t_{k+1}: every (chain, term) product, split over K, stores
+  // its partial products in slabs of the chain's workspace, which are then summed
+  // into Y_k in a fixed order (terms, then splits).
   void project(int k) {
     steps12(k);
-    ZeroList z{fb.n, (long)g.cy * 2 * g.cy, {}};
-    for (int i = 0; i < fb.n; ++i) z.p[i] = fb.c[i].y + (size_t)k * g.cy * 2 * g.cy;
-    zero_list(z, s);
     std::vector<GemmJob> d;
-    int ks = 1;
+    int ks = 2;
+    for (int t = 0; t < fb.nt; ++t) ks = std::max(ks, ksplit_for(2 * g.cy, g.cy, g.wcap[t] * g.ck[t]));
+    const long sl = 2L * g.cy * g.cy;
     for (int t = 0; t < fb.nt; ++t) {
-      ks = std::max(ks, ksplit_for(2 * g.cy, g.cy, g.wcap[t] * g.ck[t]));
       for (int i = 0; i < fb.n; ++i) {
         const FChain& c = fb.c[i];
         const FTerm& tm = c.t[t];
@@ -290,13 +291,22 @@ struct Fitter {
         GemmJob j; one(j);     // Y[(a,s')][c] += coef F2[(a,s')][(b',c')] RA[c][(b',c')]
         j.A = c.ws + l.F2[t]; j.ars = B1(tm.ab, k + 1, ck); j.acs = C_(1);
         j.B = c.ws + l.RA[t] + (size_t)(k + 1) * l.env[t]; j.brs = C_(1); j.bcs = B1(tm.ab, k + 1, ck);
-        j.C = c.y + (size_t)k * g.cy * 2 * g.cy; j.crs = C_(g.cy); j.ccs = C_(1);
+        j.C = c.ws + l.slab + (size_t)t * ks * sl; j.crs = C_(g.cy); j.ccs = C_(1);
         j.M = B1(c.yb, k, 2); j.N = B1(c.yb, k + 1); j.K = B1(tm.ab, k + 1, ck);
         j.alpha = tm.coef;
         d.push_back(j);
       }
     }
-    run(d, 1, 2 * g.cy, g.cy, mode, std::max(ks, 2));
+    run(d, 1, 2 * g.cy, g.cy, mode, ks, sl);
+    SlabSum z;
+    std::memset(&z, 0, sizeof(z));
+    z.n = fb.n; z.nq = fb.nt * ks; z.k = k; z.cap = g.cy; z.slab = sl;
+    for (int i = 0; i < fb.n; ++i) {
+      z.dst[i] = fb.c[i].y + (size_t)k * g.cy * 2 * g.cy;
+      z.src[i] = fb.c[i].ws + l.slab;
+      z.bond[i] = fb.c[i].yb;
+    }
+    slab_sum(z, s);
   }
 
   // LA^t_{k+1}[p][(b', q)] = sum_{(a, s')} Y_k[(a, s')][p] F2_t[(a, s')][(b', q)]

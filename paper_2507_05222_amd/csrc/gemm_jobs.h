@@ -33,12 +33,14 @@ struct GemmJob {
   const double* skip;       // if non-null and *skip != 0, the job is skipped
   double alpha, beta;       // C = alpha A B + beta C; split over K: C += alpha A B
 };
-// Split over K (ksplit > 1): every split adds alpha times its partial product to C
-// with FP64 atomic adds, so C must hold zeros (or the sum so far) beforehand and
-// the order of the additions is not fixed.
+// Split over K (ksplit > 1): split sp stores alpha times its partial product (beta
+// ignored, zeros for an empty K range) at C + sp * slab, a slab of its own; the
+// caller sums the slabs in a fixed order (k_slab_sum), so the result does not
+// depend on the order in which the workgroups run.
 struct GemmBatch {
   int n, maxb;
   int ksplit;               // K-splits per output tile (1: none; jobs must then have nb == 1)
+  long slab;                // doubles between the slabs of consecutive splits
   double* cnt;              // measurement counters or null
   GemmJob j[GB];
 };
@@ -62,15 +64,45 @@ __global__ void __launch_bounds__(256) k_gemm_jobs(GemmBatch gb) {
   View A{j.A + (long)bi * ev(j.sa), ev(j.ars), ev(j.acs)};
   View B{j.B + (long)bi * ev(j.sb), ev(j.brs), ev(j.bcs)};
   if (S == 1) {
-    gemm_tile<MODE, false, TS>(M, N, 0, K, A, B, j.C + (long)bi * ev(j.sc), ev(j.crs), ev(j.ccs), j.alpha, j.beta,
+    gemm_tile<MODE, TS>(M, N, 0, K, A, B, j.C + (long)bi * ev(j.sc), ev(j.crs), ev(j.ccs), j.alpha, j.beta,
                                m0, n0);
     return;
   }
   const int kc = ((K + S - 1) / S + Cfg<MODE>::BK - 1) / Cfg<MODE>::BK * Cfg<MODE>::BK;
   const int k0 = min(K, sp * kc), k1 = min(K, k0 + kc);
-  if (k0 < k1)
-    gemm_tile<MODE, true, TS>(M, N, k0, k1, A, B, j.C + (long)bi * ev(j.sc), ev(j.crs), ev(j.ccs), j.alpha, 0.0, m0,
-                              n0);
+  gemm_tile<MODE, TS>(M, N, k0, k1, A, B, j.C + (long)bi * ev(j.sc) + (long)sp * gb.slab, ev(j.crs), ev(j.ccs),
+                             j.alpha, 0.0, m0, n0);
+}
+
+// Fixed-order sum of split-product slabs into core k of a train: for chain i,
+// dst_i[(a, s, c)] = sum_{q < nq} src_i[q * slab + (a, s, c)] for a < bond[k],
+// c < bond[k + 1] (layout [a][2][cap]), and zero elsewhere in the slot.
+struct SlabSum {
+  int n, nq, k, cap;
+  long slab;
+  double* dst[QTT_BMAX];
+  const double* src[QTT_BMAX];
+  const int* bond[QTT_BMAX];
+};
+__global__ void k_slab_sum(SlabSum z) {
+  const int i = blockIdx.y;
+  if (i >= z.n) return;
+  const int nl = z.bond[i][z.k], nr = z.bond[i][z.k + 1];
+  const int S = 2 * z.cap * z.cap;
+  const gcdp src = as_global(z.src[i]);
+  const gdp dst = as_global(z.dst[i]);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < S; e += gridDim.x * blockDim.x) {
+    const int a = e / (2 * z.cap), c = e % z.cap;
+    double v = 0.0;
+    if (a < nl && c < nr)
+      for (int q = 0; q < z.nq; ++q) v += src[(long)q * z.slab + e];
+    dst[e] = v;
+  }
+}
+void slab_sum(const SlabSum& z, hipStream_t s) {
+  if (z.n > 0)
+    hipLaunchKernelGGL(k_slab_sum, dim3((unsigned)std::max(1, std::min(32, (2 * z.cap * z.cap + 255) / 256)), z.n),
+                       dim3(256), 0, s, z);
 }
 
 // Zero fill of up to QTT_BMAX buffers of len doubles (outputs of split products).
@@ -92,11 +124,12 @@ void zero_list(const ZeroList& z, hipStream_t s) {
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 // K-splits for a GEMM with few output tiles and a long K: aim at ~24 workgroups
-// of 64 x 64 tiles per job, at least 64 of K per split.
+// of 64 x 64 tiles per job, at least 64 of K per split, at most KSPLIT_MAX.
+constexpr int KSPLIT_MAX = 8;
 inline int ksplit_for(int maxM, int maxN, int Kmax) {
   const int tiles = cdiv(maxM, TILE) * cdiv(maxN, TILE);
   const int S = std::min(24 / std::max(tiles, 1), Kmax / 64);
-  return std::max(1, std::min(S, 8));
+  return std::max(1, std::min(S, KSPLIT_MAX));
 }
 
 // Launches with fewer than SMALL_GRID workgroups of 64 x 64 tiles use 32 x 32 tiles.

@@ -52,9 +52,7 @@ __device__ __forceinline__ typename Cfg<MODE>::T to_t(double v) {
 // blocks) or 32 (each wave owns one 16 x 16 block): the small tile puts four
 // times as many workgroups, each with a quarter of the dependent MFMA chain, on
 // a product whose 64 x 64 grid would leave most of the chip idle.
-// ATOM: the tile is added to C with FP64 atomic adds (split-K partial products that
-// several workgroups accumulate into one zeroed output; beta is ignored).
-template <int MODE, bool ATOM = false, int TS = TILE>
+template <int MODE, int TS = TILE>
 __device__ __forceinline__ void gemm_tile(int M, int N, int k0, int k1, View A, View B, double* C, long crs, long ccs,
                                           double alpha, double beta, int m0, int n0) {
   static_assert(TS == 64 || TS == 32, "tile edge");
@@ -156,12 +154,8 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int k0, int k1, View A, 
         if (gm < M && gn < N) {
           double val = alpha * (double)acc[bi][bj][v];
           const gdp cp = Cg + (long)gm * crs + (long)gn * ccs;
-          if constexpr (ATOM) {
-            unsafeAtomicAdd((double*)cp, val);
-          } else {
-            if (beta != 0.0) val += beta * (*cp);
-            *cp = val;
-          }
+          if (beta != 0.0) val += beta * (*cp);
+          *cp = val;
         }
       }
 }

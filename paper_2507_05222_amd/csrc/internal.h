@@ -53,7 +53,8 @@ enum KClass {
   KC_CG = 7,            // local CG vector updates
   KC_JOBS_LP = 8,       // the same GEMMs on FP32 or BF16 MFMA
   KC_ZIP_MPO = 9,       // zip-up contraction with the MPO core (k_zip_t2)
-  KC_COUNT = 10
+  KC_CG_COOP = 10,      // local CG solves in one cooperative launch each (FP64 MFMA products)
+  KC_COUNT = 11
 };
 
 namespace qttk {

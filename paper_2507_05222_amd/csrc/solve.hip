@@ -48,12 +48,13 @@ struct SGeo {
   double ltol;      // local CG: reduction of the initial local residual
   int maxit;        // CG iterations per local problem
   int lds;          // dynamic LDS budget (bytes) of the gauge-move kernels
-  int mvs;          // local matvec: K-splits of its last product (> 1: atomic accumulation)
+  int mvs;          // local matvec: K-splits of its last product (slabs summed in order by the reader)
 };
 
 // workspace layout (doubles)
 struct SLay {
-  size_t LA, RA, Lb, Rb, F1, F2, F3, Mt, Mt2, beff, r, p, Ap, dinv, sc, tmpA, gp, LM, total;
+  size_t LA, RA, Lb, Rb, F1, F2, F3, Mt, Mt2, beff, r, p, Ap, dinv, sc, tmpA, gp, LM, slab, total;
+  size_t pcu, pcP, pcs, pcf, pce;   // the one-launch local CG: operand, slabs, partial sums, flags, epoch
   size_t env, envb;
   static SLay make(int L, int cx, int ck, int cb, int W) {
     SLay l;
@@ -74,12 +75,18 @@ struct SLay {
     l.beff = o; o += al(2 * (size_t)cx * cx);
     l.r = o; o += al(2 * (size_t)cx * cx);
     l.p = o; o += al(2 * (size_t)cx * cx);
-    l.Ap = o; o += al(2 * (size_t)cx * cx);
+    l.Ap = o; o += al((size_t)KSPLIT_MAX * 2 * cx * cx);   // split slabs of the local product
     l.dinv = o; o += al(2 * (size_t)cx * cx);
     l.sc = o; o += 64;
     l.tmpA = o; o += al(4 * (size_t)cx * cx);
     l.gp = o; o += al(4 * 4 * (size_t)cx * cx);
     l.LM = o; o += al((size_t)cx * 2 * W * 2 * cx);
+    l.slab = o; o += al((size_t)KSPLIT_MAX * 2 * cx * cx);   // split products of the projection
+    l.pcu = o; o += al(2 * (size_t)cx * cx);
+    l.pcP = o; o += al((size_t)W * 2 * cx * cx);
+    l.pcs = o; o += al(4 * 256);
+    l.pcf = o; o += al(256 * 32 / 2);     // 256 flags of 128 bytes (unsigned)
+    l.pce = o; o += 64;
     l.total = o;
     return l;
   }
@@ -119,7 +126,10 @@ __global__ void k_env_init(SBatch sb, SGeo g, SLay l) {
     c.ws[l.Rb + (size_t)g.L * l.envb] = 1.0;
   }
   if (threadIdx.x < S_COUNT) c.ws[l.sc + threadIdx.x] = 0.0;
-  for (int e = threadIdx.x; e < 2 * g.cx * g.cx; e += blockDim.x) c.ws[l.Ap + e] = 0.0;   // accumulated into
+  // barrier flags, epoch and failure flag of the one-launch local CG
+  unsigned* f = reinterpret_cast<unsigned*>(c.ws + l.pcf);
+  for (int e = threadIdx.x; e < 256 * 32; e += blockDim.x) f[e] = 0u;
+  if (threadIdx.x < 2) reinterpret_cast<unsigned*>(c.ws + l.pce)[threadIdx.x] = 0u;
 }
 
 // start of a sweep: clear the maximum of the projected residuals
@@ -165,13 +175,13 @@ __device__ double block_sum(double v, double* red) {
   return t;
 }
 
-// Element e = (a 2 + s) cx + c of the local product M_eff v. With a split last
-// product (g.mvs > 1) the splits accumulate into Ap with atomic adds, so the one
-// reader of each product clears the elements it has read for the next one.
+// Element e = (a 2 + s) cx + c of the local product M_eff v: the sum, in split
+// order, of the g.mvs slabs of its split last product.
 __device__ __forceinline__ double ap_take(const SChain& c, const SGeo& g, const SLay& l, int e) {
-  const gdp ap = as_global(c.ws + l.Ap);
-  const double v = ap[e];
-  if (g.mvs > 1) ap[e] = 0.0;
+  const gcdp ap = as_global((const double*)(c.ws + l.Ap));
+  const long n = 2L * g.cx * g.cx;
+  double v = ap[e];
+  for (int q = 1; q < g.mvs; ++q) v += ap[q * n + e];
   return v;
 }
 
@@ -285,7 +295,7 @@ __global__ void __launch_bounds__(1024) k_cg_step(SBatch sb, SGeo g, SLay l) {
   } else {
     for (int e = tid; e < n; e += blockDim.x) {
       const int a = e / (2 * cx), cc = e % cx;
-      if (a < nl && cc < nr) pAp += p[e] * c.ws[l.Ap + e];
+      if (a < nl && cc < nr) pAp += p[e] * ap_take(c, g, l, e);
     }
     pAp = block_sum(pAp, red);
     alpha = pAp > 0.0 ? rz / pAp : 0.0;
@@ -311,6 +321,279 @@ __global__ void __launch_bounds__(1024) k_cg_step(SBatch sb, SGeo g, SLay l) {
     sc[S_RZ] = rz2; sc[S_RN2] = rn; sc[S_ITER] = it0 + 1.0;
     sc[S_ITERS_TOTAL] += 1.0;
     sc[S_DONE] = done ? 1.0 : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The whole local CG of a site in one cooperative launch (FP64, slot capacity <= 64)
+// ---------------------------------------------------------------------------
+// The local product is M_eff v = sum_{b'} LM_{b'} V RA_{b'}^T, with V the local
+// vector as a (2 b_k) x b_{k+1} matrix, LM_{b'} the rows of LM = LA_k A_k with MPO
+// index b' and RA_{b'}[c][c'] = RA_{k+1}[(c, b')][c']. The G = W * RB workgroups of a
+// chain split it into units (b', block of 32 rows (a, s')): a unit computes its
+// 32 x b_{k+1} block of LM_{b'} V RA_{b'}^T on FP64 MFMA, with its LM and RA tiles
+// resident in LDS for the whole solve, and stores it as slab b'. Every workgroup
+// also owns a contiguous slice of the local vector, holds the CG state of that
+// slice in registers and sums the slabs of its elements in b' order.
+// The iteration is Jacobi-preconditioned CG in the Chronopoulos-Gear arrangement
+// (both inner products of an iteration reduced together): three device-wide
+// barriers per iteration. Inner products are per-workgroup partial sums added in
+// workgroup order by every workgroup, so all take the same decisions and the
+// result does not depend on scheduling. Stop rule and counters are those of
+// k_cg_init / k_cg_step.
+constexpr int PC_THREADS = 256;
+constexpr int PC_RB = 32;           // rows (a, s') of a unit
+constexpr int PC_CAP = 64;          // largest slot capacity of the one-launch path
+constexpr int PC_PER = 8;           // slice elements per thread: 2 cx^2 / G <= 32 cx <= 8 * 256
+constexpr int PC_MAXG = 256;        // workgroups per chain (flags and partial sums)
+constexpr int PC_LDL = 2 * PC_CAP + 1, PC_LDU = PC_CAP + 1, PC_LDR = PC_CAP + 1, PC_LDT = PC_CAP + 1;
+constexpr size_t PC_LDS =
+    (size_t)(PC_RB * PC_LDL + 2 * PC_CAP * PC_LDU + PC_CAP * PC_LDR + PC_RB * PC_LDT) * sizeof(double);
+constexpr int PC_FLAG = 32;         // unsigned ints between two workgroups' flags (128 bytes)
+constexpr int PC_SPIN = 1 << 22;    // polls before a barrier wait is abandoned
+
+// Barrier of the G workgroups of one chain: each publishes its epoch in its own
+// flag after an agent-scope release of its writes; wavefront 0 of each polls all
+// G flags, then acquires. A wait that outlasts PC_SPIN polls (or sees the chain's
+// failure flag) sets the failure flag and returns false in every thread.
+__device__ bool pc_barrier(unsigned* flags, int G, int bid, unsigned epoch, int* fail, int* bad) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    if (lane == 0) __hip_atomic_store(&flags[bid * PC_FLAG], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    bool ok = true;
+    for (int spins = 0;; ++spins) {
+      bool mine = true;
+      for (int i = lane; i < G; i += 64)
+        mine = mine && (int)(__hip_atomic_load(&flags[i * PC_FLAG], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+                             epoch) >= 0;
+      if (__all(mine)) break;
+      if (spins > PC_SPIN || __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        if (lane == 0) __hip_atomic_store(fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = false;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (lane == 0) *bad = ok ? 0 : 1;
+  }
+  __syncthreads();
+  return *bad == 0;
+}
+
+// Sum of the G per-workgroup partials in slots[0 .. G), in a fixed order; every
+// wavefront computes it, with identical bits in every workgroup.
+__device__ __forceinline__ double pc_gsum(const double* slots, int G) {
+  double v = 0.0;
+  for (int i = threadIdx.x & 63; i < G; i += 64) v += slots[i];
+  return wave_sum(v);
+}
+
+// Workgroup sums of three values (fixed order), returned to every thread.
+__device__ __forceinline__ void pc_bsum3(double& a, double& b, double& c, double (*red)[PC_THREADS / 64]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double v[3] = {a, b, c};
+  wave_sum_n<3>(v);
+  __syncthreads();
+  if (lane == 0) { red[0][wave] = v[0]; red[1][wave] = v[1]; red[2][wave] = v[2]; }
+  __syncthreads();
+  a = b = c = 0.0;
+  for (int w = 0; w < PC_THREADS / 64; ++w) { a += red[0][w]; b += red[1][w]; c += red[2][w]; }
+}
+
+__global__ void __launch_bounds__(PC_THREADS) k_cg_coop(SBatch sb, SGeo g, SLay l, int G, int first, double* cnt) {
+  extern __shared__ double smem[];
+  double* LMs = smem;                               // [PC_RB][PC_LDL]   rows of LM_{b'} of this unit
+  double* Us = LMs + PC_RB * PC_LDL;                // [2 PC_CAP][PC_LDU] the operand V
+  double* RAs = Us + 2 * PC_CAP * PC_LDU;           // [PC_CAP][PC_LDR]   RA_{b'}[c][c']
+  double* Ts = RAs + PC_CAP * PC_LDR;               // [PC_RB][PC_LDT]    LM_{b'} V rows of this unit
+  __shared__ double red[3][PC_THREADS / 64];
+  __shared__ int bad;
+  if ((int)blockIdx.y >= sb.n) return;
+  const SChain& c = sb.c[blockIdx.y];
+  const int bid = blockIdx.x, tid = threadIdx.x;
+  const int k = g.k, cx = g.cx, n = 2 * cx * cx;
+  const int nl = c.xb[k], nr = c.xb[k + 1], w2 = c.ab[k + 1];
+  const int RB = (2 * cx + PC_RB - 1) / PC_RB;
+  const int bp = bid / RB, rb = bid % RB;
+  const bool unit = bp < w2 && rb * PC_RB < 2 * nl;
+  double* sc = c.ws + l.sc;
+  double* u = c.ws + l.pcu;
+  double* P = c.ws + l.pcP;
+  double* slots = c.ws + l.pcs;                     // [4][PC_MAXG]: rho, gamma, |b|^2, delta
+  unsigned* flags = reinterpret_cast<unsigned*>(c.ws + l.pcf);
+  unsigned* ep = reinterpret_cast<unsigned*>(c.ws + l.pce);
+  int* fail = reinterpret_cast<int*>(ep + 1);
+  unsigned epoch = ep[0];                           // written back by workgroup 0 at the end
+  const double rn0_prev = sc[S_RN0], pmax_prev = sc[S_PMAX], iters_prev = sc[S_ITERS_TOTAL];
+  double* X = c.x + (long)k * sl2(cx);
+  const double* LM = c.ws + l.LM;
+  const double* RA = c.ws + l.RA + (size_t)(k + 1) * l.env;
+
+  // resident tiles of the unit (zero outside the actual bonds)
+  if (unit) {
+    for (int e = tid; e < PC_RB * 2 * PC_CAP; e += PC_THREADS) {
+      const int i = e / (2 * PC_CAP), j = e % (2 * PC_CAP), q = rb * PC_RB + i;
+      LMs[i * PC_LDL + j] = (q < 2 * nl && j < 2 * nl) ? LM[((long)q * w2 + bp) * 2 * cx + j] : 0.0;
+    }
+    for (int e = tid; e < PC_CAP * PC_CAP; e += PC_THREADS) {
+      const int cc = e / PC_CAP, cp = e % PC_CAP;
+      RAs[cc * PC_LDR + cp] = (cc < nr && cp < nr) ? RA[((long)cc * w2 + bp) * cx + cp] : 0.0;
+    }
+  }
+  // the CG state of this workgroup's slice, in registers
+  const int SL = (n + G - 1) / G, e0 = bid * SL, e1 = min(n, e0 + SL);
+  double xr[PC_PER], rr[PC_PER], pr[PC_PER], sr[PC_PER], ur[PC_PER], wr[PC_PER], dr[PC_PER], br[PC_PER];
+  bool ok[PC_PER];
+#pragma unroll
+  for (int j = 0; j < PC_PER; ++j) {
+    const int e = e0 + tid + PC_THREADS * j;
+    ok[j] = e < e1 && (e / (2 * cx)) < nl && (e % cx) < nr;
+    xr[j] = ok[j] ? X[e] : 0.0;
+    dr[j] = ok[j] ? c.ws[l.dinv + e] : 0.0;
+    br[j] = ok[j] ? c.ws[l.beff + e] : 0.0;
+    rr[j] = pr[j] = sr[j] = ur[j] = wr[j] = 0.0;
+  }
+  const int lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const int r0 = (wv & 1) * 16, c0 = (wv >> 1) * 32;
+  // slabs of the unit: P[b'][(a, s')][c] <- (LM_{b'} V RA_{b'}^T)[rows of the unit]
+  auto product = [&](const double* V) {
+    for (int e = tid; e < 2 * PC_CAP * PC_CAP; e += PC_THREADS) {
+      const int j = e / PC_CAP, cc = e % PC_CAP;
+      Us[j * PC_LDU + cc] = (j < 2 * nl && cc < nr) ? V[j * cx + cc] : 0.0;
+    }
+    __syncthreads();
+    if (unit) {
+      v4d a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+      const int K1 = (2 * nl + 3) & ~3;
+      for (int kk = 0; kk < K1; kk += 4) {
+        const double av = LMs[(r0 + li) * PC_LDL + kk + lk];
+        const double b0 = Us[(kk + lk) * PC_LDU + c0 + li];
+        const double b1 = Us[(kk + lk) * PC_LDU + c0 + 16 + li];
+        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, a0, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, a1, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        Ts[(r0 + lk + 4 * v) * PC_LDT + c0 + li] = a0[v];
+        Ts[(r0 + lk + 4 * v) * PC_LDT + c0 + 16 + li] = a1[v];
+      }
+    }
+    __syncthreads();
+    if (unit) {
+      v4d a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+      const int K2 = (nr + 3) & ~3;
+      for (int kk = 0; kk < K2; kk += 4) {
+        const double av = Ts[(r0 + li) * PC_LDT + kk + lk];
+        const double b0 = RAs[(c0 + li) * PC_LDR + kk + lk];
+        const double b1 = RAs[(c0 + 16 + li) * PC_LDR + kk + lk];
+        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, a0, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, a1, 0, 0, 0);
+      }
+      double* Pb = P + (long)bp * n;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int q = rb * PC_RB + r0 + lk + 4 * v;
+        if (q < 2 * nl) {
+          if (c0 + li < nr) Pb[q * cx + c0 + li] = a0[v];
+          if (c0 + 16 + li < nr) Pb[q * cx + c0 + 16 + li] = a1[v];
+        }
+      }
+    }
+  };
+  auto slab_total = [&](int e) {
+    double v = 0.0;
+    for (int b = 0; b < w2; ++b) v += P[(long)b * n + e];
+    return v;
+  };
+
+  // r = b - A x, u = D r
+  product(X);
+  if (!pc_barrier(flags, G, bid, ++epoch, fail, &bad)) return;
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+#pragma unroll
+  for (int j = 0; j < PC_PER; ++j) {
+    const int e = e0 + tid + PC_THREADS * j;
+    if (ok[j]) {
+      rr[j] = br[j] - slab_total(e);
+      ur[j] = dr[j] * rr[j];
+      t0 += rr[j] * rr[j]; t1 += rr[j] * ur[j]; t2 += br[j] * br[j];
+    }
+    if (e < e1) u[e] = ur[j];
+  }
+  pc_bsum3(t0, t1, t2, red);
+  if (tid == 0) { slots[bid] = t0; slots[PC_MAXG + bid] = t1; slots[2 * PC_MAXG + bid] = t2; }
+  if (!pc_barrier(flags, G, bid, ++epoch, fail, &bad)) return;
+  const double rho0 = pc_gsum(slots, G);
+  double gam = pc_gsum(slots + PC_MAXG, G);
+  const double bn = pc_gsum(slots + 2 * PC_MAXG, G);
+  const double thr = fmax(g.ltol * g.ltol * (first ? rho0 : rn0_prev), c.atol2);
+  double rho = rho0, gam_prev = 0.0, alpha_prev = 0.0;
+  int its = 0;
+  bool done = (bn == 0.0 || rho0 <= thr || g.maxit <= 0);
+  while (!done) {
+    // w = A u
+    product(u);
+    if (!pc_barrier(flags, G, bid, ++epoch, fail, &bad)) return;
+    double d0 = 0.0, z1 = 0.0, z2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < PC_PER; ++j)
+      if (ok[j]) {
+        wr[j] = slab_total(e0 + tid + PC_THREADS * j);
+        d0 += wr[j] * ur[j];
+      }
+    pc_bsum3(d0, z1, z2, red);
+    if (tid == 0) slots[3 * PC_MAXG + bid] = d0;
+    if (!pc_barrier(flags, G, bid, ++epoch, fail, &bad)) return;
+    const double delta = pc_gsum(slots + 3 * PC_MAXG, G);
+    const double beta = its == 0 ? 0.0 : gam / gam_prev;
+    const double den = its == 0 ? delta : delta - beta * gam / alpha_prev;
+    if (!(den > 0.0) || !(gam > 0.0)) break;      // breakdown (exact solution or loss of definiteness)
+    const double alpha = gam / den;
+    double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < PC_PER; ++j) {
+      const int e = e0 + tid + PC_THREADS * j;
+      if (ok[j]) {
+        pr[j] = ur[j] + beta * pr[j];
+        sr[j] = wr[j] + beta * sr[j];
+        xr[j] += alpha * pr[j];
+        rr[j] -= alpha * sr[j];
+        ur[j] = dr[j] * rr[j];
+        q0 += rr[j] * rr[j]; q1 += rr[j] * ur[j];
+      }
+      if (e < e1) u[e] = ur[j];
+    }
+    pc_bsum3(q0, q1, q2, red);
+    if (tid == 0) { slots[bid] = q0; slots[PC_MAXG + bid] = q1; }
+    if (!pc_barrier(flags, G, bid, ++epoch, fail, &bad)) return;
+    rho = pc_gsum(slots, G);
+    gam_prev = gam;
+    gam = pc_gsum(slots + PC_MAXG, G);
+    alpha_prev = alpha;
+    ++its;
+    done = rho <= thr || its >= g.maxit;
+  }
+#pragma unroll
+  for (int j = 0; j < PC_PER; ++j)
+    if (ok[j]) X[e0 + tid + PC_THREADS * j] = xr[j];
+  if (bid == 0 && tid == 0) {
+    sc[S_ITER] = its;
+    sc[S_ITERS_TOTAL] = iters_prev + its;
+    sc[S_RN2] = rho;
+    sc[S_DONE] = 1.0;
+    if (first) { sc[S_RN0] = rho0; sc[S_PMAX] = fmax(pmax_prev, rho0); }
+    ep[0] = epoch;
+    if (cnt) {
+      // algorithmic work of the (its + 1) local products: LM V then (.) RA^T, actual bonds
+      const double m1 = 2.0 * nl * w2, k1 = 2.0 * nl;
+      const double fl = 2.0 * m1 * k1 * nr + 2.0 * (2.0 * nl) * ((double)w2 * nr) * nr;
+      const double by = 8.0 * (m1 * k1 + k1 * nr + (double)w2 * nr * nr + 2.0 * nl * nr);
+      atomicAdd(cnt, (its + 1) * fl);
+      atomicAdd(cnt + 1, (its + 1) * by);
+    }
   }
 }
 
@@ -513,24 +796,33 @@ struct Solver {
   }
 
   // Variational projection of M x onto the frame of the bra at site k:
-  // X_k <- LA_k M_k K_k RA_{k+1} (leaves G = M_k T[a] in F2 for la_step3).
+  // X_k <- LA_k M_k K_k RA_{k+1} (leaves G = M_k T[a] in F2 for la_step3). The last
+  // product is split over K into slabs, summed into X_k in split order.
   void project(int k, int mmode) {
     const int cx = g.cx, ck = g.ck, W = g.W;
     la_steps12(k, mmode);
-    ZeroList z{sb.n, (long)cx * 2 * cx, {}};
-    for (int i = 0; i < sb.n; ++i) z.p[i] = sb.c[i].x + (size_t)k * cx * 2 * cx;
-    zero_list(z, s);                   // the split product below accumulates into X_k
+    const long sl = 2L * cx * cx;
     GemmBatch g3 = batch(1);
     for (int i = 0; i < sb.n; ++i) {
       const SChain& c = sb.c[i];
       GemmJob& d = g3.j[i]; one(d);    // X[(a,s')][c] = G[(a,s')][(b',c')] RA[c][(b',c')]
       d.A = c.ws + l.F2; d.ars = B1(c.ab, k + 1, ck); d.acs = C_(1);
       d.B = c.ws + l.RA + (size_t)(k + 1) * l.env; d.brs = C_(1); d.bcs = B1(c.ab, k + 1, ck);
-      d.C = c.x + (size_t)k * cx * 2 * cx; d.crs = C_(cx); d.ccs = C_(1);
+      d.C = c.ws + l.slab; d.crs = C_(cx); d.ccs = C_(1);
       d.M = B1(c.xb, k, 2); d.N = B1(c.xb, k + 1); d.K = B1(c.ab, k + 1, ck);
     }
     g3.ksplit = ksplit_for(2 * cx, cx, W * ck);
+    g3.slab = sl;
     run_jobs(g3, 2 * cx, cx, mmode, s);
+    SlabSum z;
+    std::memset(&z, 0, sizeof(z));
+    z.n = sb.n; z.nq = g3.ksplit; z.k = k; z.cap = cx; z.slab = sl;
+    for (int i = 0; i < sb.n; ++i) {
+      z.dst[i] = sb.c[i].x + (size_t)k * cx * 2 * cx;
+      z.src[i] = sb.c[i].ws + l.slab;
+      z.bond[i] = sb.c[i].xb;
+    }
+    slab_sum(z, s);
   }
 
   void lb_update(int k) {
@@ -618,8 +910,8 @@ struct Solver {
   }
 
   // out = M_eff v at site k (v, out: [a][s][c], row stride cx): T = LM v, then
-  // out = T RA, the last product split over K (g.mvs > 1) with the splits added
-  // into the zeroed out by atomic adds; the CG kernels clear out as they read it.
+  // out = T RA, the last product split over K (g.mvs > 1) into slabs that the CG
+  // kernels sum in split order as they read them.
   void matvec(int k, bool v_is_x, int mmode) {
     const int cx = g.cx, W = g.W;
     GemmBatch g1 = batch(1), g3 = batch(1);
@@ -641,6 +933,7 @@ struct Solver {
       d.skip = skip;
     }
     g3.ksplit = g.mvs;
+    g3.slab = 2L * cx * cx;
     run_jobs(g1, cx * 2 * W, cx, mmode, s);
     run_jobs(g3, 2 * cx, cx, mmode, s);
   }
@@ -655,12 +948,26 @@ struct Solver {
   // that decides convergence is always exact to FP64.
   double* flags = nullptr;   // host pinned, GB entries
   bool flag_copy_failed = false;   // a failed flag read stops the enqueuing; the sweep reports it
+  int coopG = 0;             // workgroups per chain of the one-launch local CG (0: not used)
+  bool coop_failed = false;  // a cooperative launch was refused; the sweep reports it
   void local_solve(int k, int mmode) {
     SGeo gg = g;
     gg.k = k;
     beff(k);
     build_lm(k);
     hipLaunchKernelGGL(k_precond, dim3(8, sb.n), dim3(256), 0, s, sb, gg, l);
+    if (mmode == 0 && coopG > 0) {
+      int first = 1, G = coopG;
+      double* cnt = nullptr;
+      qttk::tmark(KC_CG_COOP, s);
+      cnt = qttk::tcount(KC_CG_COOP);
+      void* args[] = {(void*)&sb, (void*)&gg, (void*)&l, (void*)&G, (void*)&first, (void*)&cnt};
+      if (hipLaunchCooperativeKernel((const void*)k_cg_coop, dim3(G, sb.n), dim3(PC_THREADS), args, PC_LDS, s) !=
+          hipSuccess)
+        coop_failed = true;
+      qttk::tmark(KC_CG_COOP, s);
+      return;
+    }
     const int reps = (mmode == 0) ? 1 : 4;
     const int per = std::max(1, g.maxit / reps);
     gg.maxit = per;
@@ -729,6 +1036,7 @@ namespace qtt_solver_detail {
 double* solver_ws(qtt_ctx* ctx, size_t doubles, int* rc);
 int set_error(qtt_ctx* ctx, int code, const char* msg);
 int lds_of(qtt_ctx* ctx);
+int coop_of(qtt_ctx* ctx);
 double* pinned(qtt_ctx* ctx, size_t doubles, int* rc);
 }
 
@@ -739,7 +1047,20 @@ hipError_t solver_init(int lds) {
   hipError_t e = hipSuccess;
   for (const void* f : fns)
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_cg_coop, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PC_LDS);
   return e;
+}
+
+// Workgroups of the one-launch local CG that can be resident at once on `device`
+// (0 if the device cannot launch it cooperatively).
+int coop_capacity(int device) {
+  int coop = 0, per_cu = 0, cus = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cg_coop, PC_THREADS, PC_LDS) != hipSuccess)
+    return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  return per_cu * cus;
 }
 }
 
@@ -786,6 +1107,11 @@ extern "C" int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qt
     S.s = s;
     S.lds = lds;
     S.flags = nullptr;
+    {
+      // one-launch local CG: FP64 products, slot capacity <= 64, all workgroups resident
+      const int G = W * ((2 * cx + PC_RB - 1) / PC_RB);
+      if (opts->contract_dt == QTT_F64 && cx <= PC_CAP && G <= PC_MAXG && G * S.sb.n <= coop_of(ctx)) S.coopG = G;
+    }
     hipLaunchKernelGGL(k_transposes, dim3(L, S.sb.n), dim3(256), 0, s, S.sb, S.g, lay);
     hipLaunchKernelGGL(k_env_init, dim3(S.sb.n), dim3(256), 0, s, S.sb, S.g, lay);
     // right-canonical start (bond structure kept), right environments
@@ -814,7 +1140,7 @@ extern "C" int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qt
         if (bb[i] == 0.0) z.p[z.n++] = S.sb.c[i].x;
       zero_list(z, s);
     }
-    double* pmax = pinned(ctx, 8 * (size_t)n, &rc);
+    double* pmax = pinned(ctx, 3 * GB + 8 * (size_t)n, &rc);   // residuals, CG flags, local CG failure words
     if (rc) return rc;
     S.flags = pmax + GB;
     int sweeps = 0;
@@ -839,10 +1165,17 @@ extern "C" int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qt
       }
       ++sweeps;
       if (S.flag_copy_failed) return set_error(ctx, QTT_EHIP, "solve: copy of the CG flags failed");
+      if (S.coop_failed) return set_error(ctx, QTT_EHIP, "solve: cooperative launch of the local CG refused");
       for (int i = 0; i < S.sb.n; ++i)
-        if (hipMemcpyAsync(pmax + i, S.sb.c[i].ws + lay.sc + S_PMAX, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+        if (hipMemcpyAsync(pmax + i, S.sb.c[i].ws + lay.sc + S_PMAX, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(pmax + 2 * GB + i, S.sb.c[i].ws + lay.pce, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
           return set_error(ctx, QTT_EHIP, "solve: copy of the residual failed");
       if (hipStreamSynchronize(s) != hipSuccess) return set_error(ctx, QTT_EHIP, "solve: stream sync failed");
+      for (int i = 0; i < S.sb.n; ++i) {
+        unsigned ef[2];
+        std::memcpy(ef, pmax + 2 * GB + i, sizeof(ef));
+        if (ef[1] != 0u) return set_error(ctx, QTT_EHIP, "solve: a barrier wait of the local CG timed out");
+      }
       all_done = true;
       bool improving = false;
       for (int i = 0; i < S.sb.n; ++i) {

@@ -24,6 +24,7 @@
 #include "internal.h"
 
 extern "C" size_t qtt_ws_act_floats(int batch);
+extern "C" int qtt_ws_input_host(const double* coarse_b, double re, double alpha, float* in, double* rms);
 extern "C" int qtt_ws_forward(qtt_ctx* ctx, const float* params, const float* in, int batch, float* acts, float* out,
                               int bf16, void* stream);
 
@@ -101,16 +102,9 @@ static int learned_guess(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_flow_state* 
     return set_error(ctx, QTT_EHIP, "step: copy of the pressure right-hand side failed");
   std::vector<double> cb;
   coarse_field(hs, hb, L, cap, cb);
-  double ms = 0.0;
-  for (double x : cb) ms += x * x;
-  const double rms = std::sqrt(ms / 4096.0);
-  if (!(rms > 0.0) || !std::isfinite(rms)) return QTT_OK;
   std::vector<float> in(3 * 4096);
-  for (int e = 0; e < 4096; ++e) {
-    in[e] = (float)(cb[e] / rms);
-    in[4096 + e] = (float)(m.re / 200.0);
-    in[8192 + e] = (float)(m.alpha / 2.0);
-  }
+  double rms = 0.0;
+  if (qtt_ws_input_host(cb.data(), m.re, m.alpha, in.data(), &rms) != QTT_OK) return QTT_OK;   // b = 0: no guess
   float* din = wsf;
   float* acts = wsf + 3 * 4096;
   float* dout = acts + qtt_ws_act_floats(1);

@@ -33,17 +33,15 @@ def forces(ctx: Q.Context, cyl: Q.CCylinder, u: Q.MPS, v: Q.MPS, p: Q.MPS):
     return cd.value, cl.value
 
 
-def strouhal(t, cl, window=0.5):
-    """(St, lift amplitude) from upward zero crossings of C_L - mean over the last
-    `window` of the history, linearly interpolated (D = U = 1); St is None with
-    fewer than two crossings."""
-    t = np.asarray(t, dtype=float)
-    cl = np.asarray(cl, dtype=float)
-    n0 = int(len(t) * (1.0 - window))
-    t, y = t[n0:], cl[n0:] - cl[n0:].mean()
-    up = np.nonzero((y[:-1] < 0) & (y[1:] >= 0))[0]
-    tc = t[up] - y[up] * (t[up + 1] - t[up]) / (y[up + 1] - y[up])
-    amp = 0.5 * (cl[n0:].max() - cl[n0:].min()) if len(cl[n0:]) else 0.0
-    if len(tc) < 2:
-        return None, amp
-    return 1.0 / float(np.mean(np.diff(tc))), amp
+def strouhal(t, cl, window=0.5, min_crossings=2):
+    """(St, lift amplitude) of a lift history (qtt_strouhal_host: upward zero crossings
+    of C_L - mean over the last `window` of the samples, linearly interpolated,
+    D = U = 1); St is None with fewer than `min_crossings` crossings."""
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    cl = np.ascontiguousarray(cl, dtype=np.float64)
+    st, amp = ctypes.c_double(0), ctypes.c_double(0)
+    rc = Q.lib().qtt_strouhal_host(t.ctypes.data, cl.ctypes.data, len(t), float(window), int(min_crossings),
+                                   ctypes.byref(st), ctypes.byref(amp))
+    if rc != 0:
+        raise Q.QttError(rc, "qtt_strouhal_host")
+    return (None if np.isnan(st.value) else st.value), amp.value

@@ -123,6 +123,10 @@ def lib():
         L.qtt_timer_durations.argtypes = [vp, p(ctypes.c_double), ctypes.c_int64, p(ctypes.c_int64)]
         L.qtt_build_host.argtypes = [p(CCylinder), i32, ctypes.c_int32, vp, vp, p(ctypes.c_int32)]
         L.qtt_tt_svd_host.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, p(CTrunc), ctypes.c_int32, vp, vp]
+        L.qtt_from_dense.argtypes = [vp, vp, ctypes.c_int32, p(CTrunc), p(CMps), vp]
+        L.qtt_strouhal_host.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
+                                        p(ctypes.c_double), p(ctypes.c_double)]
+        L.qtt_ws_input_host.argtypes = [vp, ctypes.c_double, ctypes.c_double, vp, p(ctypes.c_double)]
         L.qtt_ws_act_floats.argtypes = [i32]
         L.qtt_ws_act_floats.restype = ctypes.c_size_t
         L.qtt_ws_forward.argtypes = [vp, vp, vp, i32, vp, vp, i32, vp]
@@ -397,12 +401,23 @@ def tt_svd_host(dense: np.ndarray, L: int, tol: float, chi: int, cap: int, devic
     return MPS.from_slots(slots, bonds, cap, device)
 
 
+def from_dense(ctx: "Context", dense: np.ndarray, L: int, tol: float, chi: int, cap: int, stream=None) -> MPS:
+    """qtt_from_dense: TT-SVD of a host vector of 2^L values into a new device MPS."""
+    dense = np.ascontiguousarray(dense, dtype=np.float64).ravel()
+    if dense.size != 2 ** L:
+        raise QttError(-1, f"from_dense: {dense.size} values for L = {L}")
+    out = MPS(L, cap)
+    ctx.check(lib().qtt_from_dense(ctx.h, dense.ctypes.data, L, ctypes.byref(_trunc(tol, chi)),
+                                   ctypes.byref(out.desc()), _stream(stream)))
+    return out
+
+
 # ---------------------------------------------------------------------------
 # measurement hook
 # ---------------------------------------------------------------------------
 KERNEL_CLASSES = {"zip_contract": 0, "zip_gram": 1, "zip_factor": 2, "zip_carry": 3, "rl_svd": 4,
                   "qr_moves": 5, "env_gemm": 6, "cg_update": 7, "env_gemm_lowp": 8,
-                  "zip_mpo": 9}
+                  "zip_mpo": 9, "cg_coop": 10}
 
 
 class KernelTimer:

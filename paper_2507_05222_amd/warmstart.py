@@ -39,6 +39,18 @@ def coarse(ctx: Q.Context, m: Q.MPS) -> np.ndarray:
     return g.reshape(64, 64)
 
 
+def ws_input(b: np.ndarray, re: float, alpha: float):
+    """Network input (3, 64, 64) of one block-averaged right-hand side and its scale
+    rms(b) (qtt_ws_input_host, the rule the fractional step applies)."""
+    b = np.ascontiguousarray(b, dtype=np.float64).reshape(HW)
+    x = np.empty(3 * HW, dtype=np.float32)
+    r = ctypes.c_double(0)
+    rc = Q.lib().qtt_ws_input_host(b.ctypes.data, float(re), float(alpha), x.ctypes.data, ctypes.byref(r))
+    if rc != 0:
+        raise Q.QttError(rc, "qtt_ws_input_host")
+    return x.reshape(3, 64, 64), r.value
+
+
 def _p(t: torch.Tensor):
     return ctypes.c_void_p(t.data_ptr())
 

@@ -61,10 +61,9 @@ def generate(ctx, n, chi, dt, configs, steps, log):
 
 
 def features(b, c):
-    """Network input (3, 64, 64) and the scale rms(b) of one pair."""
-    r = np.sqrt(np.mean(b ** 2))
-    x = np.stack([b / r, np.full_like(b, c[0] / 200.0), np.full_like(b, c[1] / 2.0)])
-    return x.astype(np.float32), r
+    """Network input (3, 64, 64) and the scale rms(b) of one pair (the library's rule)."""
+    from paper_2507_05222_amd import warmstart as W
+    return W.ws_input(b, c[0], c[1])
 
 
 def main():

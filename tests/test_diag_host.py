@@ -48,3 +48,30 @@ def test_strouhal_matches_oracle():
     assert abs(st - 0.192) < 2e-3
     st, amp = D.strouhal(t, 0.4 * np.sin(2 * np.pi * 0.2 * t))
     assert abs(st - 0.2) < 1e-5 and abs(amp - 0.4) < 1e-3
+
+
+def test_strouhal_edge_cases():
+    """Fewer crossings than asked for gives no Strouhal number; malformed calls are refused."""
+    from paper_2507_05222_amd import diag as D, qtt as Q
+    import pytest
+    t = np.linspace(0.0, 1.0, 101)
+    st, amp = D.strouhal(t, t, window=1.0)      # a ramp: a single upward crossing of its mean
+    assert st is None and abs(amp - 0.5) < 1e-15
+    with pytest.raises(Q.QttError):
+        D.strouhal(t[:1], t[:1])
+
+
+def test_network_input_rule():
+    """qtt_ws_input_host: channels b / rms(b), Re / 200, alpha / 2 in FP32, scale rms(b);
+    b = 0 has no scale and is refused."""
+    from paper_2507_05222_amd import qtt as Q, warmstart as W
+    import pytest
+    rng = np.random.default_rng(9)
+    b = rng.standard_normal((64, 64)) * 3.0
+    x, r = W.ws_input(b, 150.0, 1.2)
+    rms = np.sqrt(np.mean(b * b))
+    assert abs(r - rms) <= 1e-14 * rms
+    np.testing.assert_array_equal(x[0], (b / rms).astype(np.float32))
+    assert np.all(x[1] == np.float32(0.75)) and np.all(x[2] == np.float32(0.6))
+    with pytest.raises(Q.QttError, match="ENUMERIC"):
+        W.ws_input(np.zeros((64, 64)), 100.0, 0.0)

@@ -193,3 +193,27 @@ def test_apply_local(Q, ctx):
     y = Q.MPS(L, 6)
     Q.apply_local(ctx, [Q.MPO.from_cores(D)], [Q.MPS.from_cores(xc, 6)], [y])
     assert rel(R.tt_full(y.cores()), R.mpo_apply_dense(D, R.tt_full(xc))) < 1e-13
+
+
+@pytest.mark.parametrize("L,tol,chi", [(12, 0.0, 64), (14, 1e-6, 16), (10, 0.3, 4)])
+def test_from_dense_matches_oracle_tt_svd(Q, ctx, L, tol, chi):
+    """qtt_from_dense against the oracle's TT-SVD of the same vector: same bonds, the
+    same reconstruction to rounding, and the truncation bound ||x - x~|| <= tol ||x||."""
+    rng = np.random.default_rng(40 + L)
+    # a smooth field plus noise: decaying singular values at every cut
+    i = np.arange(2 ** L)
+    v = np.sin(2 * np.pi * i / 2 ** L) * np.exp(-i / 2 ** (L - 2)) + 1e-3 * rng.standard_normal(2 ** L)
+    x = Q.from_dense(ctx, v, L, tol, chi, chi)
+    ref = R.tt_svd(v, L, tol=tol, chi_max=chi)
+    assert x.bonds() == R.bonds_of(ref)
+    xf = R.tt_full(x.cores())
+    assert rel(xf, R.tt_full(ref)) < 1e-10
+    if chi >= 2 ** (L // 2):
+        assert np.linalg.norm(xf - v) <= tol * np.linalg.norm(v) + 1e-12 * np.linalg.norm(v)
+
+
+def test_from_dense_rejects_bad_input(Q, ctx):
+    with pytest.raises(Q.QttError, match="ENUMERIC"):
+        Q.from_dense(ctx, np.full(2 ** 8, np.nan), 8, 0.0, 8, 8)
+    with pytest.raises(Q.QttError):
+        Q.from_dense(ctx, np.zeros(2 ** 8), 9, 0.0, 8, 8)

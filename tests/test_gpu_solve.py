@@ -69,3 +69,40 @@ def test_poisson_c1_grid_vs_fast_solver(Q, ctx):
     info, _ = Q.poisson_solve(ctx, [P], [b], [x], Q.solve_opts(tol=1e-9, max_sweeps=2, max_local_iters=1500,
                                                                local_tol=1e-12))
     assert rel(R.tt_full(x.cores()), ref[perm]) < 1e-8, (info[0].residual, info[0].local_iters)
+
+
+def test_als_capacity_64_full_rank_matches_dense(Q, ctx):
+    """2^6 x 2^6 grid at slot capacity 64 (full rank): the local CG runs as one
+    cooperative launch with four 32-row blocks per MPO index (the C3 shape)."""
+    n = 6
+    L = 2 * n
+    A = Q.build_mpo(Q.cylinder(n, Re=100.0, dt=1e-3), Q.OP["P"])
+    Ad = R.mpo_full(A.cores())
+    bc = random_mps_cores(L, 64, seed=31)
+    b = Q.MPS.from_cores(bc, 64)
+    x = Q.MPS.from_cores(random_mps_cores(L, 64, seed=32), 64)
+    opts = Q.solve_opts(tol=1e-10, max_sweeps=4, max_local_iters=600, local_tol=1e-12)
+    info, _ = Q.poisson_solve(ctx, [A], [b], [x], opts)
+    ref = np.linalg.solve(Ad, R.tt_full(bc))
+    assert rel(R.tt_full(x.cores()), ref) < 1e-8, (info[0].residual, info[0].sweeps, info[0].local_iters)
+    assert right_orthonormal_error(x.cores()) < 1e-10
+
+
+def test_solve_is_bitwise_reproducible(Q, ctx):
+    """The same truncated solve twice (fresh contexts): identical cores, residuals and
+    iteration counts, since every reduction of the solver runs in a fixed order."""
+    n = 5
+    L = 2 * n
+    A = Q.build_mpo(Q.cylinder(n, Re=100.0, dt=1e-3), Q.OP["P"])
+    bc = random_mps_cores(L, 16, seed=33)
+    runs = []
+    for _ in range(2):
+        c = Q.Context(0)
+        b = Q.MPS.from_cores(bc, 16)
+        x = Q.MPS.from_cores(random_mps_cores(L, 16, seed=34), 16)
+        info, _ = Q.poisson_solve(c, [A], [b], [x], Q.solve_opts(tol=1e-12, max_sweeps=3, max_local_iters=80,
+                                                                local_tol=1e-2))
+        runs.append(([cc.copy() for cc in x.cores()], info[0].local_iters, info[0].residual))
+    (xa, ia, ra), (xb, ib, rb) = runs
+    assert ia == ib and ra == rb
+    assert all(np.array_equal(p, q) for p, q in zip(xa, xb))

@@ -50,14 +50,13 @@ def test_step_warm_start_is_per_state():
     F.fractional_step(shared, ops, b, opts)
     b_ref = state(2)
     F.fractional_step(Q.Context(0), ops, b_ref, opts)
-    # Split products add their partial sums with atomic adds in no fixed order, so two
-    # identical steps agree to rounding amplified by the solves (~1e-12), not bit for
-    # bit; a warm start taken from the other state changes the truncated fits by their
-    # truncation error, orders of magnitude above the bound.
+    # Every reduction runs in a fixed order, so the two steps agree bit for bit; a
+    # warm start taken from the other state would change the truncated fits by their
+    # truncation error.
     for name in ("u", "v", "p"):
         x = R.tt_full(getattr(b, name).cores())
         y = R.tt_full(getattr(b_ref, name).cores())
-        assert np.linalg.norm(x - y) <= 1e-9 * np.linalg.norm(y), name
+        assert np.array_equal(x, y), (name, np.linalg.norm(x - y) / np.linalg.norm(y))
 
 
 def test_step_warm_start_not_taken_from_a_freed_state():
@@ -95,4 +94,4 @@ def test_step_warm_start_not_taken_from_a_freed_state():
     for name in ("u", "v", "p"):
         x = R.tt_full(getattr(b, name).cores())
         y = R.tt_full(getattr(b_ref, name).cores())
-        assert np.linalg.norm(x - y) <= 1e-9 * np.linalg.norm(y), name
+        assert np.array_equal(x, y), (name, np.linalg.norm(x - y) / np.linalg.norm(y))
