@@ -156,6 +156,18 @@ int qtt_add(qtt_ctx* ctx, int n, const double* a, const qtt_mps* x, const double
  * doubles; the stream is synchronised. */
 int qtt_dot(qtt_ctx* ctx, int n, const qtt_mps* x, const qtt_mps* y, double* out, void* stream);
 
+/* qtt_dot for callers that cannot allocate device or pinned memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * FP64 inner products, written to out (DEVICE, n doubles) in stream order; no
+ * allocation and no synchronisation. Its workspace is a file-scope device array
+ * of 2^20 doubles (8 MiB) that every GPU the library runs on holds until the
+ * process ends: problems whose workspace (about 17 cap^2 doubles for cap =
+ * max(x.cap, y.cap)) exceeds it are refused with QTT_ECAPACITY, larger batches run
+ * in chunks. All calls on one GPU share that array: calls that overlap on one GPU
+ * (other streams, other contexts, other threads) race and must be serialised by
+ * the caller. */
+int qtt_dot_noalloc(qtt_ctx* ctx, int n, const qtt_mps* x, const qtt_mps* y, double* out, void* stream);
+
 /* out[i] = <x_i, A_i y_i> in FP64. HOST out; synchronises. */
 int qtt_dot_mpo(qtt_ctx* ctx, int n, const qtt_mps* x, const qtt_mpo* A, const qtt_mps* y,
                 double* out, void* stream);

@@ -24,6 +24,7 @@ struct qtt_ctx {
   int device = 0;
   int lds = 64 * 1024;
   int coop = 0;                // workgroups of the one-launch local CG resident at once (0: unavailable)
+  double* scratch = nullptr;   // this device's copy of the file-scope scratch array (qtt_dot_noalloc)
   std::string err;
   double* ws = nullptr;        // chain workspaces (device)
   size_t ws_cap = 0;           // doubles
@@ -47,6 +48,12 @@ struct qtt_ctx {
   uint64_t step_warm_gen = 0;   // the caller's state id (0 = none)
   int step_warm_L = 0, step_warm_cap = 0;
 };
+
+// Scratch of qtt_dot_noalloc: every GPU the library runs on holds its own copy of
+// this array until the process ends. Host code reaches it only through the device
+// address qtt_create obtains (ctx->scratch); the array's name is not a device address.
+constexpr size_t QTT_NOALLOC_DOUBLES = (size_t)1 << 20;   // 8 MiB
+static __device__ __align__(256) double scratch[QTT_NOALLOC_DOUBLES];
 
 namespace {
 
@@ -208,6 +215,9 @@ int qtt_create(int device, qtt_ctx** out) {
   if (e == hipSuccess) e = qtt_solver_detail::fit_init(ctx->lds);
   if (e != hipSuccess) { delete ctx; return QTT_EHIP; }
   ctx->coop = qtt_solver_detail::coop_capacity(device);
+  // device address of this device's scratch array (the device is current here)
+  e = hipGetSymbolAddress((void**)&ctx->scratch, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) { delete ctx; return QTT_EHIP; }
   *out = ctx;
   return QTT_OK;
 }
@@ -450,6 +460,45 @@ static int dot_impl(qtt_ctx* ctx, int n, const qtt_mps* x, const qtt_mpo* A, con
 
 int qtt_dot(qtt_ctx* ctx, int n, const qtt_mps* x, const qtt_mps* y, double* out, void* stream) {
   return dot_impl(ctx, n, x, nullptr, y, out, stream);
+}
+
+int qtt_dot_noalloc(qtt_ctx* ctx, int n, const qtt_mps* x, const qtt_mps* y, double* out, void* stream) {
+  if (!ctx) return QTT_EINVAL;
+  if (n < 1 || !x || !y || !out) return fail(ctx, QTT_EINVAL, "dot_noalloc: bad arguments");
+  if (!ctx->scratch) return fail(ctx, QTT_EHIP, "dot_noalloc: no scratch address");
+  int rc;
+  const int L = x[0].L, capx = x[0].cap, capy = y[0].cap;
+  for (int i = 0; i < n; ++i) {
+    if ((rc = check_mps(ctx, x[i], "dot_noalloc x")) || (rc = check_mps(ctx, y[i], "dot_noalloc y"))) return rc;
+    if (x[i].L != L || y[i].L != L || x[i].cap != capx || y[i].cap != capy)
+      return fail(ctx, QTT_ESHAPE, "dot_noalloc: problems must share L and capacities");
+  }
+  const WsLayout wl = WsLayout::make(L, std::max(capx, capy), 1, 1);
+  if (wl.total > QTT_NOALLOC_DOUBLES)
+    return fail(ctx, QTT_ECAPACITY, "dot_noalloc: one problem needs %zu doubles of scratch, the limit is %zu",
+                wl.total, QTT_NOALLOC_DOUBLES);
+  const int per = (int)std::min<size_t>(QTT_BMAX, QTT_NOALLOC_DOUBLES / wl.total);
+  hipStream_t s = (hipStream_t)stream;
+  for (int i0 = 0; i0 < n; i0 += per) {
+    Batch b;
+    b.n = std::min(per, n - i0);
+    for (int i = 0; i < b.n; ++i) {
+      Chain& c = b.c[i];
+      std::memset(&c, 0, sizeof(c));
+      c.x = x[i0 + i].data; c.xb = x[i0 + i].bond;
+      c.x2 = y[i0 + i].data; c.x2b = y[i0 + i].bond;
+      c.ws = ctx->scratch + wl.total * i;
+    }
+    Geo g = make_geo(L, capx, capx, 1, 1, 0.0, 1, 0, capy, 1, ctx->lds);
+    qttk::dot_init(b, g, s);
+    for (int k = 0; k < L; ++k) {
+      g.k = k;
+      qttk::dot_step(b, g, 0, s);
+    }
+    qttk::dot_finish(b, g, s);
+    qttk::dot_out(b, g, out + i0, s);
+  }
+  return launch_status(ctx);
 }
 
 int qtt_dot_mpo(qtt_ctx* ctx, int n, const qtt_mps* x, const qtt_mpo* A, const qtt_mps* y, double* out,

@@ -124,4 +124,5 @@ void apply_local(const Batch& b, const Geo& g, hipStream_t s);     // y <- D x, 
 void dot_init(const Batch& b, const Geo& g, hipStream_t s);
 void dot_step(const Batch& b, const Geo& g, int with_mpo, hipStream_t s);
 void dot_finish(const Batch& b, const Geo& g, hipStream_t s);
+void dot_out(const Batch& b, const Geo& g, double* out, hipStream_t s);   // device out[i] <- chain i's result
 }  // namespace qttk

@@ -648,6 +648,12 @@ __global__ void k_dot_finish(Batch b, WsLayout wl) {
   if (threadIdx.x == 0) b.c[blockIdx.x].ws[wl.scal + SC_DOT] = b.c[blockIdx.x].ws[wl.carry];
 }
 
+// out[i] <- the inner product of chain i (device output)
+__global__ void k_dot_out(Batch b, WsLayout wl, double* out) {
+  if (blockIdx.x >= b.n) return;
+  if (threadIdx.x == 0) out[blockIdx.x] = b.c[blockIdx.x].ws[wl.scal + SC_DOT];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -843,6 +849,10 @@ void dot_step(const Batch& b, const Geo& g, int with_mpo, hipStream_t s) {
 
 void dot_finish(const Batch& b, const Geo& g, hipStream_t s) {
   hipLaunchKernelGGL(k_dot_finish, dim3(b.n), dim3(64), 0, s, b, lay(g));
+}
+
+void dot_out(const Batch& b, const Geo& g, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_out, dim3(b.n), dim3(64), 0, s, b, lay(g), out);
 }
 
 }  // namespace qttk

@@ -113,6 +113,7 @@ def lib():
                               p(CTrunc), vp]
         L.qtt_dot.argtypes = [vp, i32, p(CMps), p(CMps), p(ctypes.c_double), vp]
         L.qtt_dot_mpo.argtypes = [vp, i32, p(CMps), p(CMpo), p(CMps), p(ctypes.c_double), vp]
+        L.qtt_dot_noalloc.argtypes = [vp, i32, p(CMps), p(CMps), vp, vp]
         L.qtt_apply_local.argtypes = [vp, i32, p(CMpo), p(CMps), p(CMps), vp]
         L.qtt_poisson_solve.argtypes = [vp, i32, p(CMpo), p(CMps), p(CMps), p(CSolveOpts), p(CSolveInfo), vp]
         L.qtt_fractional_step.argtypes = [vp, p(CFlowOps), p(CFlowState), p(CStepOpts), p(CStepInfo), vp]
@@ -300,6 +301,16 @@ def dot(ctx: Context, xs, ys, stream=None) -> np.ndarray:
     out = np.zeros(len(xs))
     ctx.check(lib().qtt_dot(ctx.h, len(xs), _arr(CMps, [x.desc() for x in xs]), _arr(CMps, [y.desc() for y in ys]),
                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream(stream)))
+    return out
+
+
+def dot_noalloc(ctx: Context, xs, ys, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """qtt_dot_noalloc: <x_i, y_i> into the device tensor out (float64, len(xs)), stream-ordered."""
+    if out.dtype != torch.float64 or not out.is_cuda or out.numel() < len(xs):
+        raise QttError(-1, "dot_noalloc: out must be a float64 device tensor of len(xs) values")
+    ctx.check(lib().qtt_dot_noalloc(ctx.h, len(xs), _arr(CMps, [x.desc() for x in xs]),
+                                    _arr(CMps, [y.desc() for y in ys]), ctypes.c_void_p(out.data_ptr()),
+                                    _stream(stream)))
     return out
 
 
