@@ -336,8 +336,9 @@ __global__ void __launch_bounds__(1024) k_cg_step(SBatch sb, SGeo g, SLay l) {
 // also owns a contiguous slice of the local vector, holds the CG state of that
 // slice in registers and sums the slabs of its elements in b' order.
 // The iteration is Jacobi-preconditioned CG in the Chronopoulos-Gear arrangement
-// (both inner products of an iteration reduced together): three device-wide
-// barriers per iteration. Inner products are per-workgroup partial sums added in
+// (both inner products of an iteration reduced together), with (u, A u) summed
+// from the units' shares as the slabs are formed: two device-wide barriers per
+// iteration. Inner products are per-workgroup partial sums added in
 // workgroup order by every workgroup, so all take the same decisions and the
 // result does not depend on scheduling. Stop rule and counters are those of
 // k_cg_init / k_cg_step.
@@ -458,8 +459,10 @@ __global__ void __launch_bounds__(PC_THREADS) k_cg_coop(SBatch sb, SGeo g, SLay 
   }
   const int lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int r0 = (wv & 1) * 16, c0 = (wv >> 1) * 32;
-  // slabs of the unit: P[b'][(a, s')][c] <- (LM_{b'} V RA_{b'}^T)[rows of the unit]
+  // slabs of the unit: P[b'][(a, s')][c] <- (LM_{b'} V RA_{b'}^T)[rows of the unit];
+  // returns this thread's share of the unit's part of (V, M_eff V)
   auto product = [&](const double* V) {
+    double vav = 0.0;
     for (int e = tid; e < 2 * PC_CAP * PC_CAP; e += PC_THREADS) {
       const int j = e / PC_CAP, cc = e % PC_CAP;
       Us[j * PC_LDU + cc] = (j < 2 * nl && cc < nr) ? V[j * cx + cc] : 0.0;
@@ -497,11 +500,18 @@ __global__ void __launch_bounds__(PC_THREADS) k_cg_coop(SBatch sb, SGeo g, SLay 
       for (int v = 0; v < 4; ++v) {
         const int q = rb * PC_RB + r0 + lk + 4 * v;
         if (q < 2 * nl) {
-          if (c0 + li < nr) Pb[q * cx + c0 + li] = a0[v];
-          if (c0 + 16 + li < nr) Pb[q * cx + c0 + 16 + li] = a1[v];
+          if (c0 + li < nr) {
+            Pb[q * cx + c0 + li] = a0[v];
+            vav += Us[q * PC_LDU + c0 + li] * a0[v];
+          }
+          if (c0 + 16 + li < nr) {
+            Pb[q * cx + c0 + 16 + li] = a1[v];
+            vav += Us[q * PC_LDU + c0 + 16 + li] * a1[v];
+          }
         }
       }
     }
+    return vav;
   };
   auto slab_total = [&](int e) {
     double v = 0.0;
@@ -534,19 +544,14 @@ __global__ void __launch_bounds__(PC_THREADS) k_cg_coop(SBatch sb, SGeo g, SLay 
   int its = 0;
   bool done = (bn == 0.0 || rho0 <= thr || g.maxit <= 0);
   while (!done) {
-    // w = A u
-    product(u);
-    if (!pc_barrier(flags, G, bid, ++epoch, fail, &bad)) return;
-    double d0 = 0.0, z1 = 0.0, z2 = 0.0;
-#pragma unroll
-    for (int j = 0; j < PC_PER; ++j)
-      if (ok[j]) {
-        wr[j] = slab_total(e0 + tid + PC_THREADS * j);
-        d0 += wr[j] * ur[j];
-      }
+    // w = A u in slabs; delta = (u, w) from the units' shares, published with the slabs
+    double d0 = product(u), z1 = 0.0, z2 = 0.0;
     pc_bsum3(d0, z1, z2, red);
     if (tid == 0) slots[3 * PC_MAXG + bid] = d0;
     if (!pc_barrier(flags, G, bid, ++epoch, fail, &bad)) return;
+#pragma unroll
+    for (int j = 0; j < PC_PER; ++j)
+      if (ok[j]) wr[j] = slab_total(e0 + tid + PC_THREADS * j);
     const double delta = pc_gsum(slots + 3 * PC_MAXG, G);
     const double beta = its == 0 ? 0.0 : gam / gam_prev;
     const double den = its == 0 ? delta : delta - beta * gam / alpha_prev;

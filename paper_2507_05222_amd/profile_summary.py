@@ -1,14 +1,16 @@
 #!/usr/bin/env python3
-"""Traffic summary of the batched GEMM kernel from rocprofv3 counter runs.
+"""Traffic summary of a kernel from rocprofv3 counter runs.
 
 Reads the rocpd databases of four `rocprofv3 --pmc` runs (FETCH_SIZE and WRITE_SIZE
 of the benchmark, and of a plain 256 MiB device copy for calibration) and the
 kernel-trace database of the same benchmark command, and writes the JSON that
-bench.py reports as `roofline.traffic` (HBM bytes per launch of k_gemm_jobs<0, *>,
-both tile sizes) next to the trace's average launch duration.
+bench.py reports as `roofline.traffic` (HBM bytes per launch of the kernel) next to
+the trace's average launch duration. --kernel selects the kernel: "cg_coop" (the
+one-launch local CG, the step's dominant kernel) or "gemm_jobs" (the batched FP64
+MFMA contractions, both tile sizes).
 
   python -m paper_2507_05222_amd.profile_summary --fetch F.db --write W.db \\
-      --cal-fetch CF.db --cal-write CW.db --trace T.db --out profiles/....json
+      --cal-fetch CF.db --cal-write CW.db --trace T.db --out profiles/....json [--kernel cg_coop]
 """
 from __future__ import annotations
 
@@ -18,10 +20,17 @@ import json
 import os
 import sqlite3
 
-KERNEL = "k_gemm_jobs<0,"
 COPY_KIB = 262144.0      # 2^25 doubles
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SOURCES = [os.path.join(ROOT, "paper_2507_05222_amd", "csrc", f) for f in ("gemm_jobs.h", "gemm_tile.h")]
+CSRC = os.path.join(ROOT, "paper_2507_05222_amd", "csrc")
+# name pattern in the trace, label, and the sources whose hash bench.py checks
+KERNELS = {
+    "cg_coop": ("k_cg_coop(", "k_cg_coop (one-launch local CG: FP64 MFMA products, vector updates, barriers)",
+                ["solve.hip", "device_common.h"]),
+    "gemm_jobs": ("k_gemm_jobs<0,", "k_gemm_jobs<0, 32|64> (FP64 MFMA batched contractions, both tile sizes)",
+                  ["gemm_jobs.h", "gemm_tile.h"]),
+}
+KERNEL = KERNELS["gemm_jobs"][0]
 
 
 def counter(db, name, pattern):
@@ -39,10 +48,10 @@ def trace_avg_us(db, pattern):
     return int(r[0]), float(r[1] or 0.0) / 1e3
 
 
-def source_hash():
+def source_hash(files):
     h = hashlib.sha256()
-    for f in SOURCES:
-        with open(f, "rb") as fh:
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -51,21 +60,23 @@ def main():
     ap = argparse.ArgumentParser()
     for a in ("fetch", "write", "cal_fetch", "cal_write", "trace", "out"):
         ap.add_argument("--" + a.replace("_", "-"), required=True)
-    ap.add_argument("--workload", default="cylinder O-grid 2^10x2^10, chi=64, fast path, one step (warm-up 0)")
+    ap.add_argument("--workload", default="cylinder O-grid 2^10x2^10, chi=64, mixed path")
+    ap.add_argument("--kernel", default="cg_coop", choices=sorted(KERNELS))
     a = ap.parse_args()
-    nf, fetch = counter(a.fetch, "FETCH_SIZE", KERNEL)
-    nw, write = counter(a.write, "WRITE_SIZE", KERNEL)
+    pat, label, files = KERNELS[a.kernel]
+    nf, fetch = counter(a.fetch, "FETCH_SIZE", pat)
+    nw, write = counter(a.write, "WRITE_SIZE", pat)
     _, cf = counter(a.cal_fetch, "FETCH_SIZE", "copyBuffer")
     _, cw = counter(a.cal_write, "WRITE_SIZE", "copyBuffer")
-    nt, avg = trace_avg_us(a.trace, KERNEL)
+    nt, avg = trace_avg_us(a.trace, pat)
     out = {
-        "kernel": "k_gemm_jobs<0, 32|64> (FP64 MFMA batched contractions, both tile sizes)",
+        "kernel": label,
         "workload": a.workload,
         "dispatches": nf, "dispatches_write_run": nw,
         "fetch_kib_per_dispatch": round(fetch, 3), "write_kib_per_dispatch": round(write, 3),
         "copy_kib": COPY_KIB, "copy_fetch_kib": cf, "copy_write_kib": cw,
         "fetch_factor": round(COPY_KIB / cf, 4), "write_factor": round(COPY_KIB / cw, 4),
-        "kernel_source_sha256_16": source_hash(),
+        "kernel_source_sha256_16": source_hash(files),
         "kernel_trace_avg_us": round(avg, 2), "kernel_trace_dispatches": nt,
     }
     with open(a.out, "w") as f:

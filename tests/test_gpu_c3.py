@@ -14,6 +14,22 @@ def test_c3_fp64_steps_match_oracle():
         assert info.poisson.residual < 1e-7, (s, info.poisson.residual)
 
 
+def test_c3_mixed_path_within_band():
+    """The mixed path of the benchmark at full size: FP64 fits, FP32-MFMA Hadamard
+    products, FP64 solves to 1e-8 with the learned warm start of the pressure solve.
+    Every field stays within the 3e-3 |J|-weighted relative L2 band of the FD oracle
+    (Sec. 4's error measure) at every step."""
+    from tests.c3_case import run
+    used = 0
+    for s, (errs, info) in enumerate(run(6, dtype="f64", product="f32", solver_dtype="f64", learned=True,
+                                         tol=1e-8)):
+        assert max(errs.values()) <= 3e-3, (s, errs)
+        used += info.warm_used
+    # the guess of the network or the previous pressure, whichever rates lower, is the
+    # start of every pressure solve (both choices are the method; none may break it)
+    assert 0 <= used <= 6
+
+
 def test_c3_wall_forces_match_oracle():
     """Drag and lift from the library's row read-out (App. C) and force formula
     (App. F) on the TT state against the oracle's forces on its FD fields."""

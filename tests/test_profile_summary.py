@@ -67,3 +67,16 @@ def test_bench_scales_counters_by_the_copy_calibration(tmp_path, monkeypatch):
     path.write_text(json.dumps(t))
     assert bench.measured_profile() is None
 
+
+
+def test_cg_kernel_pattern_and_bench_sources(tmp_path):
+    """The local-CG entry selects k_cg_coop only, and its source hash is the one
+    bench.py checks before it reports the committed traffic."""
+    import bench
+    coop = "(anonymous namespace)::k_cg_coop((anonymous namespace)::SBatch, (anonymous namespace)::SGeo, " \
+           "(anonymous namespace)::SLay, int, int, double*)"
+    db = _trace_db(tmp_path / "t.db", [(coop, 0, 400000), (coop, 0, 200000), (GEMM32, 0, 10 ** 9)])
+    pat, _, files = PS.KERNELS["cg_coop"]
+    n, avg = PS.trace_avg_us(db, pat)
+    assert n == 2 and avg == pytest.approx(300.0)
+    assert PS.source_hash(files) == bench.kernel_source_hash()
