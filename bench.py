@@ -83,14 +83,14 @@ def clone(Q, m):
     return c
 
 
-def dense(Q, F, m, n):
+def dense(Q, F, m, n, order="interleaved"):
     cores = m.cores()
     out = np.ones((1, 1))
     for c in cores:
         out = (out @ c.reshape(c.shape[0], -1)).reshape(-1, c.shape[2])
     q = out.reshape(-1)
     N = 2 ** n
-    perm = F.grid_to_qtt_order(np.arange(N * N, dtype=float).reshape(N, N)).astype(np.int64)
+    perm = F.grid_to_qtt_order(np.arange(N * N, dtype=float).reshape(N, N), order).astype(np.int64)
     grid = np.empty(N * N)
     grid[perm] = q
     return grid.reshape(N, N)
@@ -181,20 +181,33 @@ def sweep(args):
             torch.cuda.empty_cache()
 
 
+CASES = {
+    # transient cylinder of the C3 workload: 2^10 x 2^10, r_out 20, App. G perturbation 1e-2
+    "c3": dict(n=10, r_out=20.0, Re=200.0, alpha=0.0, dt=2e-3, A0=1e-2, chi=64),
+    # the paper's rotating cylinder (Sec. 4.2, Table 2): G1 = 2^8 x 2^8, outer diameter
+    # 32 D, Re = 100, rotation rate 1 (Eq. rot_bc), dt = 2e-3, uniform start
+    "rotating_g1": dict(n=8, r_out=16.0, Re=100.0, alpha=1.0, dt=2e-3, A0=0.0, chi=40),
+}
+
+
 def shedding(args):
-    """Transient cylinder (C3: 2^10 x 2^10, Re = 200, dt = 2e-3, chi = 64, App. G
-    perturbation) on the FP64 path, drag and lift every 10 steps, resumable: the TT
+    """A long transient run on the FP64 path (--case: "c3", the 2^10 x 2^10 transient
+    cylinder, or "rotating_g1", the paper's rotating cylinder of Table 2; --chi
+    overrides the case's bond), drag and lift every 10 steps, resumable: the TT
     state, the step count and the force history go to --ckpt-out after every 1000
     steps and are read from --ckpt-in if given. Once --shedding-steps are done the
-    Strouhal number and lift amplitude (upward zero crossings of C_L, last half of
-    the run) are printed as one JSON line."""
+    Strouhal number, lift amplitude and mean lift (upward zero crossings of C_L, last
+    half of the run) are printed as one JSON line."""
     import torch
     from paper_2507_05222_amd import diag as D, flow as F, qtt as Q
     from qtt_inputs import random_mps_cores
-    n, chi, Re, dt, A0 = 10, 64, 200.0, 2e-3, 1e-2
+    c = dict(CASES[args.case])
+    if args.chi_case:
+        c["chi"] = args.chi_case
+    n, chi, Re, dt, A0 = c["n"], c["chi"], c["Re"], c["dt"], c["A0"]
     L = 2 * n
     ctx = Q.Context(0)
-    ops = F.FlowOps(n, 20.0, Re, dt)
+    ops = F.FlowOps(n, c["r_out"], Re, dt, c["alpha"])
     so = lambda tol, sw: Q.solve_opts(tol=tol, max_sweeps=sw, max_local_iters=80, local_tol=args.local_tol, dtype="f64")
     opts = F.step_opts(dt, tol=1e-8, chi=chi, dtype="f64", product="f64", helm=so(1e-8, 4), pois=so(args.pois_tol, 8))
     st = F.FlowState(Q.MPS(L, chi), Q.MPS(L, chi), Q.MPS(L, chi))
@@ -207,7 +220,7 @@ def shedding(args):
     else:
         u0, v0 = initial_fields(n, A0)
         for k, f in (("u", u0), ("v", v0)):
-            getattr(st, k).copy_(Q.tt_svd_host(F.grid_to_qtt_order(f), L, 1e-14, chi, chi))
+            getattr(st, k).copy_(Q.from_dense(ctx, F.grid_to_qtt_order(f), L, 1e-14, chi, chi))
         st.p.copy_(Q.MPS.from_cores(random_mps_cores(L, chi, seed=0), chi))
         done, hist = 0, []
 
@@ -231,15 +244,19 @@ def shedding(args):
             torch.cuda.synchronize()
             save()
         if done % 250 == 0 or done == end:
-            print(f"[bench] shedding step {done}/{total} t {done * dt:.2f} C_D {hist[-1][1]:.5f} C_L {hist[-1][2]:.3e} "
-                  f"{(done - s0) / (time.perf_counter() - t0):.2f} steps/s", file=sys.stderr, flush=True)
-    out = {"workload": f"transient cylinder Re={Re:g}, O-grid 2^{n}x2^{n}, chi={chi}, dt={dt:g}, A0={A0:g}",
+            print(f"[bench] {args.case} step {done}/{total} t {done * dt:.2f} C_D {hist[-1][1]:.5f} "
+                  f"C_L {hist[-1][2]:.3e} {(done - s0) / (time.perf_counter() - t0):.2f} steps/s",
+                  file=sys.stderr, flush=True)
+    out = {"workload": f"{args.case}: Re={Re:g}, rotation rate {c['alpha']:g}, O-grid 2^{n}x2^{n}, "
+                       f"r_out={c['r_out']:g}, chi={chi}, dt={dt:g}, A0={A0:g}",
            "steps_done": done, "steps_total": total,
            "steps_per_s_this_call": round((done - s0) / (time.perf_counter() - t0), 3)}
     if done >= total and hist:
         h = np.array(hist)
         St, amp = D.strouhal(h[:, 0] * dt, h[:, 2])
-        out.update({"St": St, "lift_amplitude": amp, "C_D_mean_last_half": float(h[len(h) // 2:, 1].mean())})
+        half = h[len(h) // 2:]
+        out.update({"St": St, "lift_amplitude": amp, "C_L_mean_last_half": float(half[:, 2].mean()),
+                    "C_D_mean_last_half": float(half[:, 1].mean())})
     print(json.dumps(out), flush=True)
 
 
@@ -382,6 +399,8 @@ def main():
                     help="local CG stop of the solves: reduction of each local residual")
     ap.add_argument("--product", default="f32", help="MFMA type of the mixed path's Hadamard products")
     ap.add_argument("--no-learned", action="store_true", help="mixed path without the learned warm start")
+    ap.add_argument("--order", default="interleaved", choices=["interleaved", "concatenated"],
+                    help="bit order of the fields and operators (the learned warm start needs interleaved)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-ensemble", type=int, default=20,
                     help="steps per process of the CPU ensemble measurement (0: skip)")
@@ -396,8 +415,10 @@ def main():
                     help="steady cylinder Re=40 on 2^8 x 2^8, chi 32: FP64 vs FP32-MFMA contractions, forces vs the oracle")
     ap.add_argument("--steady-steps", type=int, default=2000)
     ap.add_argument("--shedding", action="store_true",
-                    help="transient cylinder Re=200 (C3) on the FP64 path with forces every 10 steps, resumable")
+                    help="long transient run (--case c3 or rotating_g1) on the FP64 path, forces every 10 steps, resumable")
     ap.add_argument("--shedding-steps", type=int, default=20000)
+    ap.add_argument("--case", default="c3", choices=["c3", "rotating_g1"], help="case of the --shedding run")
+    ap.add_argument("--chi-case", type=int, default=0, help="bond of the --shedding run (0: the case's)")
     ap.add_argument("--steps-per-call", type=int, default=20000)
     ap.add_argument("--ckpt-in", default=None)
     ap.add_argument("--ckpt-out", default=None)
@@ -425,11 +446,11 @@ def main():
     Re, dt, A0, alpha = 200.0, 2e-3, 1e-2, 0.0
     ctx = Q.Context(0)
     t0 = time.perf_counter()
-    ops = F.FlowOps(n, 20.0, Re, dt, alpha)
+    ops = F.FlowOps(n, 20.0, Re, dt, alpha, order=args.order)
     setup_s = time.perf_counter() - t0
     u_init, v_init = initial_fields(n, A0)
-    U0 = Q.from_dense(ctx, F.grid_to_qtt_order(u_init), L, 1e-14, chi, chi)
-    V0 = Q.from_dense(ctx, F.grid_to_qtt_order(v_init), L, 1e-14, chi, chi)
+    U0 = Q.from_dense(ctx, F.grid_to_qtt_order(u_init, args.order), L, 1e-14, chi, chi)
+    V0 = Q.from_dense(ctx, F.grid_to_qtt_order(v_init, args.order), L, 1e-14, chi, chi)
     from qtt_inputs import random_mps_cores     # seeded cold start of the first pressure solve
     P0 = Q.MPS.from_cores(random_mps_cores(L, chi, seed=0), chi)
 
@@ -440,7 +461,8 @@ def main():
     # plain: FP64 throughout; mixed: FP64 fits (their errors feed the divergence),
     # Hadamard products on FP32 (or BF16) MFMA, learned warm start of the pressure solve
     plain = F.step_opts(dt, tol=1e-8, chi=chi, dtype="f64", product="f64", helm=so(4), pois=so(8))
-    ws = None if (args.no_learned or n < 6) else W.WarmStart.load(ctx, Re, alpha, chi=16, bf16=True)
+    ws = (None if (args.no_learned or n < 6 or args.order != "interleaved")
+          else W.WarmStart.load(ctx, Re, alpha, chi=16, bf16=True))
     mixed = F.step_opts(dt, tol=1e-8, chi=chi, dtype="f64", product=args.product, helm=so(4), pois=so(8), warm=ws)
 
     fields, sps, infos = {}, {}, {}
@@ -450,7 +472,7 @@ def main():
         st, t, inf = run_path(Q, F, ctx, ops, U0, V0, P0, opts, args.warmup, args.steps, name)
         sps[name] = args.steps / t
         infos[name] = inf
-        fields[name] = {k: dense(Q, F, getattr(st, k), n) for k in ("u", "v", "p")}
+        fields[name] = {k: dense(Q, F, getattr(st, k), n, args.order) for k in ("u", "v", "p")}
         if name == "mixed":
             st_m = st
 
@@ -505,7 +527,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if reported == "plain" else f"f64+{args.product}",
         "data": "synthetic",
-        "config": {"workload": f"cylinder O-grid 2^{n}x2^{n} ({L} interleaved cores), chi={chi}, Re={Re:g}, "
+        "config": {"workload": f"cylinder O-grid 2^{n}x2^{n} ({L} {args.order} cores), chi={chi}, Re={Re:g}, "
                                f"dt={dt:g}, App. G perturbation A0={A0:g}",
                    "reported_path": reported,
                    "mixed_path": f"FP64 fits (gradients, right-hand sides, divergence, projection), "

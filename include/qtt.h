@@ -340,12 +340,17 @@ enum {
   QTT_VEC_BX_U = 100, QTT_VEC_BZ_U, QTT_VEC_BX_V, QTT_VEC_BZ_V, QTT_VEC_BL_U,
   QTT_VEC_BL_V, QTT_VEC_BW, QTT_VEC_ABSJ
 };
+enum { QTT_ORDER_INTERLEAVED = 0, QTT_ORDER_CONCATENATED = 1 };
 typedef struct {
   int32_t n;       /* cores per axis; L = 2n, grid 2^n x 2^n */
   double r_out;    /* outer radius (cylinder diameter 1)      */
   double Re, dt;   /* Reynolds number, time step              */
   double alpha;    /* wall rotation rate                       */
   double u_inf;    /* far-field velocity (x direction)         */
+  int32_t order;   /* bit order of every encoding (Sec. 3.2.1): QTT_ORDER_INTERLEAVED,
+                      core 2m <- bit m of i and core 2m+1 <- bit m of j, or
+                      QTT_ORDER_CONCATENATED, cores 0..n-1 <- the bits of i and cores
+                      n..2n-1 <- those of j; MSB first in both */
 } qtt_cylinder;
 
 int qtt_build_host(const qtt_cylinder* cyl, int which, int32_t cap, double* out,
@@ -353,11 +358,13 @@ int qtt_build_host(const qtt_cylinder* cyl, int which, int32_t cap, double* out,
 
 /* ---- diagnostics (Sec. 4, App. C, App. F) --------------------------------- */
 
-/* Rows of a field in interleaved order (App. C: the eta bits of the row index
- * are fixed, the remaining train over the xi bits is contracted): out (HOST,
- * nrows * 2^(L/2) doubles) receives row rows[r] (0 <= rows[r] < 2^(L/2), 0 = the
- * first interior row next to the wall) at out + r * 2^(L/2). Synchronises the stream. */
-int qtt_read_rows(qtt_ctx* ctx, const qtt_mps* x, int nrows, const int32_t* rows, double* out, void* stream);
+/* Rows of a field in bit order `order` (QTT_ORDER_*; App. C: the eta bits of the
+ * row index are fixed, the remaining train over the xi bits is contracted): out
+ * (HOST, nrows * 2^(L/2) doubles) receives row rows[r] (0 <= rows[r] < 2^(L/2),
+ * 0 = the first interior row next to the wall) at out + r * 2^(L/2). Synchronises
+ * the stream. */
+int qtt_read_rows(qtt_ctx* ctx, const qtt_mps* x, int nrows, const int32_t* rows, int32_t order, double* out,
+                  void* stream);
 
 /* Drag and lift coefficients (App. F, Eq. liftdrag; rho = U = D = 1) of the
  * cylinder cyl from rows (HOST, 5 * 2^n doubles): u on rows 0 and 1, v on rows 0

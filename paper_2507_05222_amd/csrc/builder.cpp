@@ -163,14 +163,23 @@ void scale_rows(Stencil& S, const std::vector<double>& f) {
 // TT encodings
 // ---------------------------------------------------------------------------
 
-// Interleaved MSB-first position of grid point (i, j): bits i_1 j_1 i_2 j_2 ...
+// Bit order of the encodings of the current qtt_build_host call (QTT_ORDER_*),
+// per thread: interleaved i_1 j_1 i_2 j_2 ... or concatenated i_1 .. i_n j_1 .. j_n
+// (Sec. 3.2.1), MSB first in both.
+thread_local int t_order = QTT_ORDER_INTERLEAVED;
+
+// Position of grid point (i, j) in the dense vector of the current order.
 size_t qidx(int i, int j, int n) {
+  if (t_order == QTT_ORDER_CONCATENATED) return ((size_t)i << n) | (size_t)j;
   size_t q = 0;
   for (int m = 0; m < n; ++m) {
     q = (q << 2) | ((size_t)((i >> (n - 1 - m)) & 1) << 1) | (size_t)((j >> (n - 1 - m)) & 1);
   }
   return q;
 }
+
+// Is core k a digit of the eta (row) index in the current order?
+bool eta_core(int k, int n) { return t_order == QTT_ORDER_CONCATENATED ? k < n : (k % 2 == 0); }
 
 std::vector<double> to_qtt_order(const std::vector<double>& f, int n) {
   const int N = 1 << n;
@@ -196,13 +205,15 @@ double shift_digit(int s, int cl, int o, int r, int cr) {
 }
 
 // MPO of the 2D shift u(i+di, j+dj), zero outside 0 <= i+di < N, periodic in j.
-// Bond state (c_eta, c_xi), 4 states; interleaved order: core 2m = eta digit m.
+// Bond state (c_eta, c_xi), 4 states: each carry flows from its coordinate's least
+// significant digit to its most significant one and passes unchanged through the
+// cores of the other coordinate, so one automaton serves both bit orders.
 HostTT shift_mpo(int n, int di, int dj) {
   const int L = 2 * n;
   HostTT T;
   T.L = L; T.d = 4;
   for (int k = 0; k < L; ++k) {
-    const bool eta = (k % 2 == 0);
+    const bool eta = eta_core(k, n);
     const int wl = (k == 0) ? 1 : 4, wr = (k == L - 1) ? 1 : 4;
     std::vector<double> core((size_t)wl * 4 * wr, 0.0);
     for (int a = 0; a < wl; ++a)
@@ -349,7 +360,13 @@ int write_mps(const HostTT& T, int32_t cap, double* out, int32_t* bond_out, int3
 extern "C" int qtt_build_host(const qtt_cylinder* cyl, int which, int32_t cap, double* out,
                               int32_t* bond_out, int32_t* need) {
   if (!cyl || cyl->n < 1 || cyl->n > 13 || !(cyl->r_out > 0.5)) return QTT_EINVAL;
+  if (cyl->order != QTT_ORDER_INTERLEAVED && cyl->order != QTT_ORDER_CONCATENATED) return QTT_EINVAL;
   if (out && !bond_out) return QTT_EINVAL;
+  struct OrderScope {      // the bit order of this call's encodings, restored on return
+    int saved;
+    explicit OrderScope(int o) : saved(t_order) { t_order = o; }
+    ~OrderScope() { t_order = saved; }
+  } order_scope(cyl->order);
   const int n = cyl->n;
   const Grid g(n, cyl->r_out);
   const int N = g.N;

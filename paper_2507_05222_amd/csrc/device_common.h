@@ -42,6 +42,27 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
+// dst(e, src(e)) for e < count, the workgroup's loads issued eight per thread at a
+// time before any is waited for (a loop with one load per iteration would pay a
+// full memory round trip per element).
+template <class Src, class Dst>
+__device__ __forceinline__ void stage8(int count, Src src, Dst dst) {
+  constexpr int B = 8;
+  for (int base = 0; base < count; base += B * (int)blockDim.x) {
+    double t[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      const int e = base + (int)threadIdx.x + q * (int)blockDim.x;
+      t[q] = e < count ? src(e) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      const int e = base + (int)threadIdx.x + q * (int)blockDim.x;
+      if (e < count) dst(e, t[q]);
+    }
+  }
+}
+
 // Value of v in lane l (l uniform over the wavefront).
 __device__ __forceinline__ double lane_value(double v, int l) {
   const unsigned long long b = __builtin_bit_cast(unsigned long long, v);

@@ -1,5 +1,5 @@
 // Read-out of grid rows from a QTT field (App. C: fixing the eta bits of the
-// interleaved index leaves a train over the xi bits, contracted to 2^n values)
+// index leaves a train over the xi bits, contracted to 2^n values)
 // for the diagnostics of Sec. 4 (wall forces, App. F). Host FP64 after one copy
 // of the cores; the time step never calls it.
 #include <hip/hip_runtime.h>
@@ -13,11 +13,13 @@ namespace qtt_solver_detail {
 int set_error(qtt_ctx* ctx, int code, const char* msg);
 }
 
-extern "C" int qtt_read_rows(qtt_ctx* ctx, const qtt_mps* x, int nrows, const int32_t* rows, double* out, void* stream) {
+extern "C" int qtt_read_rows(qtt_ctx* ctx, const qtt_mps* x, int nrows, const int32_t* rows, int32_t order,
+                             double* out, void* stream) {
   using qtt_solver_detail::set_error;
   if (!ctx) return QTT_EINVAL;
-  if (!x || !x->data || !x->bond || !rows || !out || nrows < 1 || x->d != 2 || x->L < 2 || (x->L & 1))
-    return set_error(ctx, QTT_EINVAL, "read_rows: needs an interleaved binary train and host buffers");
+  if (!x || !x->data || !x->bond || !rows || !out || nrows < 1 || x->d != 2 || x->L < 2 || (x->L & 1) ||
+      (order != QTT_ORDER_INTERLEAVED && order != QTT_ORDER_CONCATENATED))
+    return set_error(ctx, QTT_EINVAL, "read_rows: needs a binary train of 2n cores, a bit order and host buffers");
   const int L = x->L, n = L / 2, cap = x->cap, N = 1 << n;
   for (int r = 0; r < nrows; ++r)
     if (rows[r] < 0 || rows[r] >= N) return set_error(ctx, QTT_EINVAL, "read_rows: row index out of range");
@@ -37,8 +39,10 @@ extern "C" int qtt_read_rows(qtt_ctx* ctx, const qtt_mps* x, int nrows, const in
     int q = 1;
     for (int k = 0; k < L; ++k) {
       const int a0 = bl[k], b0 = bl[k + 1];
-      if ((k & 1) == 0) {                       // eta bit m = k/2 of the row index, MSB first
-        const int bit = (I >> (n - 1 - k / 2)) & 1;
+      const bool eta = order == QTT_ORDER_CONCATENATED ? k < n : (k & 1) == 0;
+      if (eta) {                                // eta bit m of the row index, MSB first
+        const int m = order == QTT_ORDER_CONCATENATED ? k : k / 2;
+        const int bit = (I >> (n - 1 - m)) & 1;
         std::vector<double> nv((size_t)q * b0, 0.0);
         for (int t = 0; t < q; ++t)
           for (int a = 0; a < a0; ++a) {

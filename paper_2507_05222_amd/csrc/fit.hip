@@ -164,10 +164,7 @@ __global__ void __launch_bounds__(1024) k_fit_lr_qr(FBatch fb, FGeo g, FLay l) {
   double* X = (need <= (size_t)g.lds) ? smem : (c.ws + l.gp);
   double* Yk = c.y + (long)k * sl2(cap);
   const int S = cap * 2 * cap;
-  for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
-    const int j = e / m, i = e % m;
-    X[e] = Yk[(long)i * cap + j];
-  }
+  stage8(m * n, [&](int e) { return Yk[(long)(e % m) * cap + e / m]; }, [&](int e, double v) { X[e] = v; });
   __syncthreads();
   if (fast) {
     for (int e = threadIdx.x; e < S; e += blockDim.x) Yk[e] = 0.0;
@@ -199,10 +196,10 @@ __global__ void __launch_bounds__(1024) k_fit_rl_lq(FBatch fb, FGeo g, FLay l) {
   double* X = (need <= (size_t)g.lds) ? smem : (c.ws + l.gp);
   double* Yk = c.y + (long)k * sl2(cap);
   const int S = cap * 2 * cap;
-  for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
-    const int a = e / m, rho = e % m, s = rho / mb, bb = rho % mb;
-    X[e] = Yk[(long)a * 2 * cap + s * cap + bb];
-  }
+  stage8(m * n, [&](int e) {
+    const int a = e / m, rho = e % m;
+    return Yk[(long)a * 2 * cap + (rho / mb) * cap + rho % mb];
+  }, [&](int e, double v) { X[e] = v; });
   __syncthreads();
   if (fast) {
     for (int e = threadIdx.x; e < S; e += blockDim.x) Yk[e] = 0.0;

@@ -95,7 +95,13 @@ __global__ void k_slab_sum(SlabSum z) {
     const int a = e / (2 * z.cap), c = e % z.cap;
     double v = 0.0;
     if (a < nl && c < nr)
-      for (int q = 0; q < z.nq; ++q) v += src[(long)q * z.slab + e];
+      for (int q0 = 0; q0 < z.nq; q0 += 8) {       // eight loads in flight, added in slab order
+        double t[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t[q] = (q0 + q < z.nq) ? src[(long)(q0 + q) * z.slab + e] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v += t[q];
+      }
     dst[e] = v;
   }
 }

@@ -376,10 +376,10 @@ __global__ void __launch_bounds__(FACT_THREADS) k_rl_svd(Batch b, Geo g, WsLayou
   double* X = in_lds ? smem : (c.ws + wl.gpart);
   double* V = X + (size_t)m * nb;
   const double* src = from_tmp ? (c.ws + wl.tmpA) : (c.y + (long)k * slot(cap, 2));
-  for (int e = threadIdx.x; e < m * nb; e += blockDim.x) {
-    const int a = e / m, rho = e % m, s = rho / mb, bb = rho % mb;
-    X[e] = src[(long)a * 2 * cap + s * cap + bb];
-  }
+  stage8(m * nb, [&](int e) {
+    const int a = e / m, rho = e % m;
+    return src[(long)a * 2 * cap + (rho / mb) * cap + rho % mb];
+  }, [&](int e, double v) { X[e] = v; });
   for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) V[e] = ((e % nb) == (e / nb)) ? 1.0 : 0.0;
   __syncthreads();
   jacobi_cols(X, m, m, nb, V, nb, &flag, g.cnt);
@@ -464,10 +464,7 @@ __global__ void __launch_bounds__(FACT_THREADS) k_lr_qr(Batch b, Geo g, WsLayout
   double* X = in_lds ? smem : (c.ws + wl.gpart);
   double* Q = X + (size_t)m * n;
   const double* src = from_tmp ? (c.ws + wl.tmpA) : (c.y + (long)k * slot(cap, 2));
-  for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
-    const int j = e / m, i = e % m;     // i = a*2 + s
-    X[e] = src[(long)i * cap + j];
-  }
+  stage8(m * n, [&](int e) { return src[(long)(e % m) * cap + e / m]; }, [&](int e, double v) { X[e] = v; });
   if (threadIdx.x == 0) rk = r;
   __syncthreads();
   householder(X, m, n, rdiag, tau);

@@ -433,15 +433,30 @@ __global__ void __launch_bounds__(PC_THREADS) k_cg_coop(SBatch sb, SGeo g, SLay 
   const double* LM = c.ws + l.LM;
   const double* RA = c.ws + l.RA + (size_t)(k + 1) * l.env;
 
-  // resident tiles of the unit (zero outside the actual bonds)
+  // resident tiles of the unit (zero outside the actual bonds); every load of a
+  // thread is issued before the first is waited for
   if (unit) {
-    for (int e = tid; e < PC_RB * 2 * PC_CAP; e += PC_THREADS) {
-      const int i = e / (2 * PC_CAP), j = e % (2 * PC_CAP), q = rb * PC_RB + i;
-      LMs[i * PC_LDL + j] = (q < 2 * nl && j < 2 * nl) ? LM[((long)q * w2 + bp) * 2 * cx + j] : 0.0;
+    constexpr int NT = PC_RB * 2 * PC_CAP / PC_THREADS, NR = PC_CAP * PC_CAP / PC_THREADS;
+    double tl[NT], tr[NR];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const int e = tid + PC_THREADS * q, i = e / (2 * PC_CAP), j = e % (2 * PC_CAP), row = rb * PC_RB + i;
+      tl[q] = (row < 2 * nl && j < 2 * nl) ? LM[((long)row * w2 + bp) * 2 * cx + j] : 0.0;
     }
-    for (int e = tid; e < PC_CAP * PC_CAP; e += PC_THREADS) {
-      const int cc = e / PC_CAP, cp = e % PC_CAP;
-      RAs[cc * PC_LDR + cp] = (cc < nr && cp < nr) ? RA[((long)cc * w2 + bp) * cx + cp] : 0.0;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int e = tid + PC_THREADS * q, cc = e / PC_CAP, cp = e % PC_CAP;
+      tr[q] = (cc < nr && cp < nr) ? RA[((long)cc * w2 + bp) * cx + cp] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const int e = tid + PC_THREADS * q;
+      LMs[(e / (2 * PC_CAP)) * PC_LDL + e % (2 * PC_CAP)] = tl[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int e = tid + PC_THREADS * q;
+      RAs[(e / PC_CAP) * PC_LDR + e % PC_CAP] = tr[q];
     }
   }
   // the CG state of this workgroup's slice, in registers
@@ -463,9 +478,20 @@ __global__ void __launch_bounds__(PC_THREADS) k_cg_coop(SBatch sb, SGeo g, SLay 
   // returns this thread's share of the unit's part of (V, M_eff V)
   auto product = [&](const double* V) {
     double vav = 0.0;
-    for (int e = tid; e < 2 * PC_CAP * PC_CAP; e += PC_THREADS) {
-      const int j = e / PC_CAP, cc = e % PC_CAP;
-      Us[j * PC_LDU + cc] = (j < 2 * nl && cc < nr) ? V[j * cx + cc] : 0.0;
+    {
+      // the operand into LDS: all 32 loads of a thread in flight at once
+      constexpr int NU = 2 * PC_CAP * PC_CAP / PC_THREADS;
+      double tv[NU];
+#pragma unroll
+      for (int q = 0; q < NU; ++q) {
+        const int e = tid + PC_THREADS * q, j = e / PC_CAP, cc = e % PC_CAP;
+        tv[q] = (j < 2 * nl && cc < nr) ? V[j * cx + cc] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < NU; ++q) {
+        const int e = tid + PC_THREADS * q;
+        Us[(e / PC_CAP) * PC_LDU + e % PC_CAP] = tv[q];
+      }
     }
     __syncthreads();
     if (unit) {
@@ -513,9 +539,16 @@ __global__ void __launch_bounds__(PC_THREADS) k_cg_coop(SBatch sb, SGeo g, SLay 
     }
     return vav;
   };
+  // sum of the slabs at element e in b' order, eight loads in flight at a time
   auto slab_total = [&](int e) {
     double v = 0.0;
-    for (int b = 0; b < w2; ++b) v += P[(long)b * n + e];
+    for (int b0 = 0; b0 < w2; b0 += 8) {
+      double t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[q] = (b0 + q < w2) ? P[(long)(b0 + q) * n + e] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v += t[q];
+    }
     return v;
   };
 
@@ -619,10 +652,10 @@ __global__ void __launch_bounds__(1024) k_rl_qr(SBatch sb, SGeo g, SLay l) {
   double* X = (need <= (size_t)g.lds) ? smem : (c.ws + l.gp);
   double* Yk = c.x + (long)k * sl2(cap);
   const int S = cap * 2 * cap;
-  for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
-    const int a = e / m, rho = e % m, s = rho / mb, bb = rho % mb;
-    X[e] = Yk[(long)a * 2 * cap + s * cap + bb];
-  }
+  stage8(m * n, [&](int e) {
+    const int a = e / m, rho = e % m;
+    return Yk[(long)a * 2 * cap + (rho / mb) * cap + rho % mb];
+  }, [&](int e, double v) { X[e] = v; });
   __syncthreads();
   if (fast) {
     for (int e = threadIdx.x; e < S; e += blockDim.x) Yk[e] = 0.0;
@@ -646,10 +679,8 @@ __global__ void __launch_bounds__(1024) k_rl_qr(SBatch sb, SGeo g, SLay l) {
   auto lb = [&](int t, int j) { return t == j ? rdiag[j] : (t > j ? X[(long)t * m + j] : 0.0); };
   wg_gemm_f64(2 * np, r, n, la, lb, T, cap);
   __syncthreads();
-  for (int e = threadIdx.x; e < S; e += blockDim.x) {
-    const int a0 = e / (2 * cap), j = e % cap;
-    Yp[e] = (a0 < np && j < r) ? T[e] : 0.0;
-  }
+  stage8(S, [&](int e) { return (e / (2 * cap) < np && e % cap < r) ? T[e] : 0.0; },
+         [&](int e, double v) { Yp[e] = v; });
   if (threadIdx.x == 0) c.xb[k] = r;
 }
 
@@ -669,10 +700,7 @@ __global__ void __launch_bounds__(1024) k_lr_qr_keep(SBatch sb, SGeo g, SLay l) 
   double* X = (need <= (size_t)g.lds) ? smem : (c.ws + l.gp);
   double* Yk = c.x + (long)k * sl2(cap);
   const int S = cap * 2 * cap;
-  for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
-    const int j = e / m, i = e % m;
-    X[e] = Yk[(long)i * cap + j];
-  }
+  stage8(m * n, [&](int e) { return Yk[(long)(e % m) * cap + e / m]; }, [&](int e, double v) { X[e] = v; });
   __syncthreads();
   if (fast) {
     for (int e = threadIdx.x; e < S; e += blockDim.x) Yk[e] = 0.0;
@@ -695,10 +723,7 @@ __global__ void __launch_bounds__(1024) k_lr_qr_keep(SBatch sb, SGeo g, SLay l) 
   auto lb = [&](int t, int nu) { return Yn[(long)t * 2 * cap + nu]; };
   wg_gemm_f64(r, 2 * cap, n, la, lb, T, 2 * cap);
   __syncthreads();
-  for (int e = threadIdx.x; e < S; e += blockDim.x) {
-    const int j = e / (2 * cap);
-    Yn[e] = (j < r) ? T[e] : 0.0;
-  }
+  stage8(S, [&](int e) { return (e / (2 * cap) < r) ? T[e] : 0.0; }, [&](int e, double v) { Yn[e] = v; });
   if (threadIdx.x == 0) c.xb[k + 1] = r;
 }
 

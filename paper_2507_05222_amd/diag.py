@@ -10,21 +10,22 @@ import numpy as np
 from . import qtt as Q
 
 
-def read_rows(ctx: Q.Context, m: Q.MPS, rows) -> np.ndarray:
-    """Rows (0 = next to the wall) of a 2^n x 2^n field, shape (len(rows), 2^n)."""
+def read_rows(ctx: Q.Context, m: Q.MPS, rows, order=0) -> np.ndarray:
+    """Rows (0 = next to the wall) of a 2^n x 2^n field in bit order `order`
+    (0 interleaved, 1 concatenated), shape (len(rows), 2^n)."""
     rows = np.ascontiguousarray(rows, dtype=np.int32)
     N = 2 ** (m.L // 2)
     out = np.empty((len(rows), N))
-    ctx.check(Q.lib().qtt_read_rows(ctx.h, ctypes.byref(m.desc()), len(rows), rows.ctypes.data, out.ctypes.data,
-                                    Q._stream()))
+    ctx.check(Q.lib().qtt_read_rows(ctx.h, ctypes.byref(m.desc()), len(rows), rows.ctypes.data,
+                                    Q.ORDERS.get(order, order), out.ctypes.data, Q._stream()))
     return out
 
 
 def forces(ctx: Q.Context, cyl: Q.CCylinder, u: Q.MPS, v: Q.MPS, p: Q.MPS):
     """(C_D, C_L) of the state (App. F)."""
-    ru = read_rows(ctx, u, [0, 1])
-    rv = read_rows(ctx, v, [0, 1])
-    rp = read_rows(ctx, p, [0])
+    ru = read_rows(ctx, u, [0, 1], cyl.order)
+    rv = read_rows(ctx, v, [0, 1], cyl.order)
+    rp = read_rows(ctx, p, [0], cyl.order)
     rows = np.ascontiguousarray(np.concatenate([ru.ravel(), rv.ravel(), rp.ravel()]))
     cd, cl = ctypes.c_double(0), ctypes.c_double(0)
     rc = Q.lib().qtt_forces_host(ctypes.byref(cyl), rows.ctypes.data, ctypes.byref(cd), ctypes.byref(cl))

@@ -14,9 +14,10 @@ from . import qtt as Q
 class FlowOps:
     """Operators (MPOs) and boundary vectors of a 2^n x 2^n O-grid (Sec. 3.2.3)."""
 
-    def __init__(self, n, r_out=20.0, Re=100.0, dt=1e-3, alpha=0.0, u_inf=1.0, device="cuda"):
+    def __init__(self, n, r_out=20.0, Re=100.0, dt=1e-3, alpha=0.0, u_inf=1.0, device="cuda", order="interleaved"):
         self.n, self.L = n, 2 * n
-        self.cyl = Q.cylinder(n, r_out, Re, dt, alpha, u_inf)
+        self.order = order
+        self.cyl = Q.cylinder(n, r_out, Re, dt, alpha, u_inf, order)
         names = ("DX", "DZ", "DXP", "DZP", "WX", "WZ", "HS", "P")
         built = {k: Q.build_host(self.cyl, Q.OP[k]) for k in names}
         # operators applied in one batched call share one slot capacity
@@ -82,10 +83,13 @@ def fractional_step(ctx: Q.Context, ops: FlowOps, st: FlowState, opts: Q.CStepOp
     return info
 
 
-def grid_to_qtt_order(field: np.ndarray) -> np.ndarray:
-    """(2^n, 2^n) grid array -> dense vector in the interleaved MSB-first order of the library."""
+def grid_to_qtt_order(field: np.ndarray, order="interleaved") -> np.ndarray:
+    """(2^n, 2^n) grid array -> dense vector in the library's MSB-first bit order:
+    interleaved (i_1 j_1 i_2 j_2 ...) or concatenated (i_1 .. i_n j_1 .. j_n)."""
     N = field.shape[0]
     n = int(np.log2(N))
+    if order == "concatenated":
+        return np.ascontiguousarray(field, dtype=np.float64).ravel().copy()
     i, j = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
     q = np.zeros_like(i)
     for m in range(n):

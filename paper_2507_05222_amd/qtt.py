@@ -87,9 +87,13 @@ class CStepInfo(ctypes.Structure):
                 ("warm_used", ctypes.c_int32), ("warm_energy", ctypes.c_double), ("prev_energy", ctypes.c_double)]
 
 
+ORDERS = {"interleaved": 0, "concatenated": 1}
+
+
 class CCylinder(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("r_out", ctypes.c_double), ("Re", ctypes.c_double),
-                ("dt", ctypes.c_double), ("alpha", ctypes.c_double), ("u_inf", ctypes.c_double)]
+                ("dt", ctypes.c_double), ("alpha", ctypes.c_double), ("u_inf", ctypes.c_double),
+                ("order", ctypes.c_int32)]
 
 
 _lib = None
@@ -135,7 +139,7 @@ def lib():
         L.qtt_ws_mse.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         L.qtt_ws_adam_step.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_float, vp]
         L.qtt_ws_coarse.argtypes = [vp, p(CMps), vp, vp]
-        L.qtt_read_rows.argtypes = [vp, p(CMps), i32, vp, vp, vp]
+        L.qtt_read_rows.argtypes = [vp, p(CMps), i32, vp, ctypes.c_int32, vp, vp]
         L.qtt_forces_host.argtypes = [p(CCylinder), vp, p(ctypes.c_double), p(ctypes.c_double)]
         _lib = L
     return _lib
@@ -368,8 +372,9 @@ def poisson_solve(ctx: Context, As, bs, xs, opts: CSolveOpts, stream=None, raise
 # ---------------------------------------------------------------------------
 # host-side setup (operators, initial fields)
 # ---------------------------------------------------------------------------
-def cylinder(n, r_out=20.0, Re=100.0, dt=1e-3, alpha=0.0, u_inf=1.0) -> CCylinder:
-    return CCylinder(int(n), float(r_out), float(Re), float(dt), float(alpha), float(u_inf))
+def cylinder(n, r_out=20.0, Re=100.0, dt=1e-3, alpha=0.0, u_inf=1.0, order="interleaved") -> CCylinder:
+    return CCylinder(int(n), float(r_out), float(Re), float(dt), float(alpha), float(u_inf),
+                     ORDERS.get(order, order))
 
 
 def build_host(cyl: CCylinder, which: int, cap: int | None = None):

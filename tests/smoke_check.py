@@ -8,13 +8,13 @@ from oracle.grid import OGrid
 from qtt_inputs import noise_fields, random_mps_cores
 
 
-def c1_initial(n=5, chi=8, tol=1e-10):
+def c1_initial(n=5, chi=8, tol=1e-10, order="interleaved"):
     """Uniform flow plus seed-0 Gaussian noise (sigma 1e-3), compressed by the
     library's TT-SVD at (tol, chi); returns dense grid fields and QTT-order vectors."""
     from paper_2507_05222_amd import qtt as Q
     L = 2 * n
     nz = noise_fields(n, n, 1e-3, seed=0)
-    perm = R.grid_perm(n, n)
+    perm = R.grid_perm(n, n, order)
     out = []
     for f in (1.0 + nz[0], nz[1]):
         m = Q.tt_svd_host(f.ravel()[perm], L, tol, chi, chi)
@@ -26,12 +26,12 @@ def c1_initial(n=5, chi=8, tol=1e-10):
 
 
 def run_c1(cap=32, n=5, Re=100.0, dt=1e-3, trunc_tol=1e-13, dtype="f64", helm_dtype=None, pois_dtype=None,
-           product_dtype=None):
+           product_dtype=None, order="interleaved", alpha=0.0):
     from paper_2507_05222_amd import flow as F, qtt as Q
     L = 2 * n
     ctx = Q.Context(0)
-    (u0, mu), (v0, mv) = c1_initial(n)
-    ops = F.FlowOps(n, 20.0, Re, dt)
+    (u0, mu), (v0, mv) = c1_initial(n, order=order)
+    ops = F.FlowOps(n, 20.0, Re, dt, alpha, order=order)
     u = Q.MPS(L, cap); v = Q.MPS(L, cap)
     Q.add(ctx, 1.0, [mu], 0.0, [mu], [u], tol=0.0, chi=cap)
     Q.add(ctx, 1.0, [mv], 0.0, [mv], [v], tol=0.0, chi=cap)
@@ -42,9 +42,9 @@ def run_c1(cap=32, n=5, Re=100.0, dt=1e-3, trunc_tol=1e-13, dtype="f64", helm_dt
     info = F.fractional_step(ctx, ops, st, F.step_opts(dt, tol=trunc_tol, chi=cap, dtype=dtype, helm=helm, pois=pois,
                                                        product=product_dtype))
     g = OGrid(n, n)
-    S = fd.FDSolver(g, Re, dt)
+    S = fd.FDSolver(g, Re, dt, alpha=alpha)
     ref = S.step(u0, v0, return_stages=True)
-    perm = R.grid_perm(n, n)
+    perm = R.grid_perm(n, n, order)
     res = {}
     for name, m in (("u", st.u), ("v", st.v), ("p", st.p)):
         q = R.tt_full(m.cores())

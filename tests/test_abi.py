@@ -31,17 +31,17 @@ def test_exports_every_declared_symbol(lib):
     assert not missing, missing
 
 
-@pytest.mark.parametrize("alpha", [0.0, 0.7])
-def test_builder_operators_match_oracle(alpha):
+@pytest.mark.parametrize("alpha,order", [(0.0, "interleaved"), (0.7, "interleaved"), (0.7, "concatenated")])
+def test_builder_operators_match_oracle(alpha, order):
     from oracle import fd, qttref as R
     from oracle.grid import OGrid
     from paper_2507_05222_amd import qtt as Q
     import scipy.sparse as sp
     n = 4
-    cyl = Q.cylinder(n, r_out=20.0, Re=100.0, dt=1e-3, alpha=alpha)
+    cyl = Q.cylinder(n, r_out=20.0, Re=100.0, dt=1e-3, alpha=alpha, order=order)
     g = OGrid(n, n)
     S = fd.FDSolver(g, 100.0, 1e-3, alpha=alpha)
-    perm = R.grid_perm(n, n)
+    perm = R.grid_perm(n, n, order)
     x = np.random.default_rng(0).standard_normal(4 ** n)
     jh = np.sqrt(S.ops.absJ)
     ops = {Q.OP["DX"]: S.Dx, Q.OP["DZ"]: S.Dz, Q.OP["DXP"]: S.Dx_p, Q.OP["DZP"]: S.Dz_p, Q.OP["LAP"]: S.Lap,
