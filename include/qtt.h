@@ -282,7 +282,10 @@ typedef struct {
  * context keeps the step's intermediate trains, and when the previous step on
  * the context advanced the same state (same u, v, p storage) the fits start
  * from them, otherwise from a random sketch (one more sweep).
- * With opts->warm (n >= 6 cores per axis, state->p.cap == state->u.cap): b is
+ * With opts->warm (n >= 6 cores per axis, state->p.cap == state->u.cap), on a step
+ * whose state->p is not the previous pressure of this state on this context (the
+ * state's first step, or another state stepped since; a running simulation keeps
+ * its previous pressure, the better start, and pays nothing): b is
  * block-averaged to the 64 x 64 grid (its last 2(n-6) cores contracted with
  * [1/2, 1/2]), the network predicts the coarse pressure, which is compressed by
  * TT-SVD to bond warm->chi, prolonged piecewise constantly (2(n-6) appended
@@ -394,7 +397,8 @@ int qtt_tt_svd_host(const double* dense, int32_t L, int32_t d, const qtt_trunc* 
  * (b, Re/200, alpha/2) on the 64 x 64 block-averaged grid (rows eta with zero
  * padding, columns xi with periodic padding) to a coarse pressure, which the
  * caller turns into an initial guess of qtt_poisson_solve. Channels 3 -> 32 ->
- * 32 -> 32 -> 1, tanh after layers 1-3. All buffers are DEVICE float arrays,
+ * 32 -> 32 -> 1, the taps of layers 1-4 spaced 1, 2, 4, 8 apart (receptive field
+ * 31 x 31), tanh after layers 1-3. All buffers are DEVICE float arrays,
  * NCHW with H = W = 64, owned by the caller; calls are stream-ordered.
  * Parameter layout: for layer l, w_l[co][ci][3][3] then b_l[co]. */
 #define QTT_WS_NPARAMS 19681

@@ -2,7 +2,8 @@
 
 The network is not part of the paper (its counterpart there is a Poisson
 preconditioner, App. G); it is specified by the library's API: four 3x3
-convolution layers on 64 x 64 fields, channels 3 -> 32 -> 32 -> 32 -> 1, tanh
+convolution layers on 64 x 64 fields, channels 3 -> 32 -> 32 -> 32 -> 1, the taps
+of layer l spaced DILATION[l] = 1, 2, 4, 8 apart (receptive field 31 x 31), tanh
 after the first three, zero padding along rows (eta), periodic padding along
 columns (xi). Parameters are one flat vector: for each layer the weights
 w[co][ci][3][3] followed by the bias b[co].
@@ -16,6 +17,7 @@ from __future__ import annotations
 import numpy as np
 
 CHANNELS = [(3, 32), (32, 32), (32, 32), (32, 1)]
+DILATION = [1, 2, 4, 8]
 N_PARAMS = sum(co * ci * 9 + co for ci, co in CHANNELS)
 
 
@@ -44,26 +46,26 @@ def shifted(x, di, dj):
     return out
 
 
-def conv(x, w, b):
-    """x [B][ci][H][W] -> [B][co][H][W]: b[co] + sum w[co][ci][di+1][dj+1] x[ci][i+di][j+dj]."""
+def conv(x, w, b, d=1):
+    """x [B][ci][H][W] -> [B][co][H][W]: b[co] + sum w[co][ci][di+1][dj+1] x[ci][i+d di][j+d dj]."""
     B, _, H, W = x.shape
     co = w.shape[0]
     y = np.zeros((B, co, H, W)) + b[None, :, None, None]
     for di in (-1, 0, 1):
         for dj in (-1, 0, 1):
-            xs = shifted(x, di, dj)
+            xs = shifted(x, d * di, d * dj)
             y += np.einsum("oc,bchw->bohw", w[:, :, di + 1, dj + 1], xs)
     return y
 
 
-def conv_adjoint(g, w):
-    """Adjoint of conv in x: gx[ci][i][j] = sum w[co][ci][di+1][dj+1] g[co][i-di][j-dj]."""
+def conv_adjoint(g, w, d=1):
+    """Adjoint of conv in x: gx[ci][i][j] = sum w[co][ci][di+1][dj+1] g[co][i-d di][j-d dj]."""
     B, _, H, W = g.shape
     ci = w.shape[1]
     gx = np.zeros((B, ci, H, W))
     for di in (-1, 0, 1):
         for dj in (-1, 0, 1):
-            gx += shifted(np.einsum("oc,bohw->bchw", w[:, :, di + 1, dj + 1], g), -di, -dj)
+            gx += shifted(np.einsum("oc,bohw->bchw", w[:, :, di + 1, dj + 1], g), -d * di, -d * dj)
     return gx
 
 
@@ -73,7 +75,7 @@ def forward(params, x):
     acts = []
     h = x
     for l, (w, b) in enumerate(layers):
-        h = conv(h, w, b)
+        h = conv(h, w, b, DILATION[l])
         if l < 3:
             h = np.tanh(h)
         acts.append(h)
@@ -94,15 +96,16 @@ def grad(params, x, target):
     grads = []
     for l in range(3, -1, -1):
         w, _ = layers[l]
+        d = DILATION[l]
         xin = x if l == 0 else acts[l - 1]
         gw = np.zeros_like(w)
         for di in (-1, 0, 1):
             for dj in (-1, 0, 1):
-                gw[:, :, di + 1, dj + 1] = np.einsum("bohw,bchw->oc", g, shifted(xin, di, dj))
+                gw[:, :, di + 1, dj + 1] = np.einsum("bohw,bchw->oc", g, shifted(xin, d * di, d * dj))
         gb = g.sum(axis=(0, 2, 3))
         grads.append((gw, gb))
         if l > 0:
-            g = conv_adjoint(g, w) * (1.0 - acts[l - 1] ** 2)
+            g = conv_adjoint(g, w, d) * (1.0 - acts[l - 1] ** 2)
     grads.reverse()
     return np.concatenate([np.concatenate([gw.ravel(), gb]) for gw, gb in grads])
 

@@ -315,7 +315,9 @@ extern "C" int qtt_fractional_step(qtt_ctx* ctx, const qtt_flow_ops* ops, qtt_fl
       g.L = L; g.capx = cap; g.capy = o->rhs_out->cap; g.d = 2;
       qttk::copy_mps(b, g, s);
     }
-    if (o->warm && (rc = learned_guess(ctx, ops, st, o, T, L, cap, chi, wsf, info, stream))) return rc;
+    // the learned guess competes with state->p only when state->p is not this state's
+    // previous pressure (its first step on the context, or another state ran since)
+    if (o->warm && !warm && (rc = learned_guess(ctx, ops, st, o, T, L, cap, chi, wsf, info, stream))) return rc;
     qtt_solve_info pi;
     qtt_solve_opts po = o->poisson;
     rc = qtt_poisson_solve(ctx, 1, &ops->P, &T[BT], &st->p, &po, &pi, stream);

@@ -1,6 +1,7 @@
 // Learned warm start of the pressure solve: a four-layer 3x3 convolutional
 // network on the 64 x 64 coarse grid (rows: eta, zero padding; columns: xi,
-// periodic padding), 3 -> 32 -> 32 -> 32 -> 1 channels, tanh after the first
+// periodic padding), 3 -> 32 -> 32 -> 32 -> 1 channels, the taps of layer l spaced
+// DIL[l] = 1, 2, 4, 8 apart (receptive field 31 x 31), tanh after the first
 // three layers. Training in FP32 (forward, backward, Adam); the forward pass can
 // round its operands to BF16 (FP32 accumulation) for inference.
 //
@@ -18,6 +19,7 @@ namespace {
 constexpr int H = 64, Wd = 64, HW = H * Wd;
 constexpr int CIN[4] = {3, 32, 32, 32};
 constexpr int COUT[4] = {32, 32, 32, 1};
+constexpr int DIL[4] = {1, 2, 4, 8};
 
 __host__ __device__ constexpr int wsize(int l) { return (l == 0 ? 3 : 32) * (l == 3 ? 1 : 32) * 9; }
 __host__ __device__ constexpr int bsize(int l) { return l == 3 ? 1 : 32; }
@@ -32,11 +34,12 @@ __device__ __forceinline__ float rbf16(float x) {   // round to nearest even BF1
   return __uint_as_float(r & 0xFFFF0000u);
 }
 
-// out[b][co][i][j] = act(bias[co] + sum_{ci,di,dj} w[co][ci][di][dj] in[b][ci][i+di-1][(j+dj-1) mod 64])
+// out[b][co][i][j] = act(bias[co] + sum_{ci,di,dj} w[co][ci][di][dj] in[b][ci][i+d(di-1)][(j+d(dj-1)) mod 64])
 // one thread per output pixel; grid (HW / 256, cout, B)
 template <bool BF>
 __global__ void __launch_bounds__(256) k_conv_fwd(const float* __restrict__ in, int cin, const float* __restrict__ w,
-                                                   const float* __restrict__ bias, int cout, int act, float* __restrict__ out) {
+                                                   const float* __restrict__ bias, int cout, int act, int d,
+                                                   float* __restrict__ out) {
   extern __shared__ float ws[];                       // weights of this output channel: cin * 9
   const int co = blockIdx.y, b = blockIdx.z;
   for (int t = threadIdx.x; t < cin * 9; t += blockDim.x) {
@@ -53,11 +56,11 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const float* __restrict__ in, 
     const float* ip = ib + (size_t)ci * HW;
 #pragma unroll
     for (int di = 0; di < 3; ++di) {
-      const int ii = i + di - 1;
+      const int ii = i + d * (di - 1);
       if (ii < 0 || ii >= H) continue;
 #pragma unroll
       for (int dj = 0; dj < 3; ++dj) {
-        const int jj = (j + dj - 1 + Wd) % Wd;
+        const int jj = (j + d * (dj - 1) + Wd) % Wd;
         const float x = ip[ii * Wd + jj];
         acc += ws[ci * 9 + di * 3 + dj] * (BF ? rbf16(x) : x);
       }
@@ -75,7 +78,8 @@ __global__ void k_tanh_bwd(float* __restrict__ g, const float* __restrict__ y, s
 // gradient of the weights and bias of one layer: one workgroup per (co, ci),
 // the nine tap sums over (b, i, j) by a fixed-order block reduction
 __global__ void __launch_bounds__(256) k_conv_bwd_w(const float* __restrict__ in, int cin, const float* __restrict__ g,
-                                                     int cout, int B, float* __restrict__ gw, float* __restrict__ gb) {
+                                                     int cout, int B, int d, float* __restrict__ gw,
+                                                     float* __restrict__ gb) {
   const int co = blockIdx.x, ci = blockIdx.y;
   float s[10];
 #pragma unroll
@@ -86,11 +90,11 @@ __global__ void __launch_bounds__(256) k_conv_bwd_w(const float* __restrict__ in
     const float* ip = in + ((size_t)b * cin + ci) * HW;
 #pragma unroll
     for (int di = 0; di < 3; ++di) {
-      const int ii = i + di - 1;
+      const int ii = i + d * (di - 1);
       const bool ok = ii >= 0 && ii < H;
 #pragma unroll
       for (int dj = 0; dj < 3; ++dj) {
-        const int jj = (j + dj - 1 + Wd) % Wd;
+        const int jj = (j + d * (dj - 1) + Wd) % Wd;
         s[di * 3 + dj] += ok ? gv * ip[ii * Wd + jj] : 0.f;
       }
     }
@@ -109,10 +113,10 @@ __global__ void __launch_bounds__(256) k_conv_bwd_w(const float* __restrict__ in
   if (threadIdx.x == 9 && ci == 0) gb[co] = red[9][0];
 }
 
-// gradient of the input: gin[b][ci][i][j] = sum_{co,di,dj} w[co][ci][di][dj] g[b][co][i-di+1][j-dj+1]
+// gradient of the input: gin[b][ci][i][j] = sum_{co,di,dj} w[co][ci][di][dj] g[b][co][i-d(di-1)][j-d(dj-1)]
 // (the transposed stencil with the same padding rules); grid (HW / 256, cin, B)
 __global__ void __launch_bounds__(256) k_conv_bwd_x(const float* __restrict__ g, int cout, const float* __restrict__ w,
-                                                     int cin, float* __restrict__ gin) {
+                                                     int cin, int d, float* __restrict__ gin) {
   const int ci = blockIdx.y, b = blockIdx.z;
   const int pix = blockIdx.x * blockDim.x + threadIdx.x;
   if (pix >= HW) return;
@@ -123,11 +127,11 @@ __global__ void __launch_bounds__(256) k_conv_bwd_x(const float* __restrict__ g,
     const float* wp = w + ((size_t)co * cin + ci) * 9;
 #pragma unroll
     for (int di = 0; di < 3; ++di) {
-      const int oi = i - di + 1;
+      const int oi = i - d * (di - 1);
       if (oi < 0 || oi >= H) continue;
 #pragma unroll
       for (int dj = 0; dj < 3; ++dj) {
-        const int oj = (j - dj + 1 + Wd) % Wd;
+        const int oj = (j - d * (dj - 1) + Wd) % Wd;
         acc += wp[di * 3 + dj] * gp[oi * Wd + oj];
       }
     }
@@ -191,8 +195,10 @@ extern "C" int qtt_ws_forward(qtt_ctx* ctx, const float* params, const float* in
     const float* b = w + wsize(l);
     dim3 grid(HW / 256, COUT[l], batch);
     const size_t lds = (size_t)CIN[l] * 9 * sizeof(float);
-    if (bf16) hipLaunchKernelGGL(k_conv_fwd<true>, grid, dim3(256), lds, s, x, CIN[l], w, b, COUT[l], l < 3 ? 1 : 0, y);
-    else hipLaunchKernelGGL(k_conv_fwd<false>, grid, dim3(256), lds, s, x, CIN[l], w, b, COUT[l], l < 3 ? 1 : 0, y);
+    if (bf16)
+      hipLaunchKernelGGL(k_conv_fwd<true>, grid, dim3(256), lds, s, x, CIN[l], w, b, COUT[l], l < 3 ? 1 : 0, DIL[l], y);
+    else
+      hipLaunchKernelGGL(k_conv_fwd<false>, grid, dim3(256), lds, s, x, CIN[l], w, b, COUT[l], l < 3 ? 1 : 0, DIL[l], y);
     x = y;
   }
   hipError_t e = hipGetLastError();
@@ -216,10 +222,12 @@ extern "C" int qtt_ws_backward(qtt_ctx* ctx, const float* params, const float* i
     const float* w = params + woff(l);
     float* gw = grads + woff(l);
     float* gb = gw + wsize(l);
-    hipLaunchKernelGGL(k_conv_bwd_w, dim3(COUT[l], CIN[l]), dim3(256), 0, s, xin, CIN[l], g, COUT[l], batch, gw, gb);
+    hipLaunchKernelGGL(k_conv_bwd_w, dim3(COUT[l], CIN[l]), dim3(256), 0, s, xin, CIN[l], g, COUT[l], batch, DIL[l],
+                       gw, gb);
     if (l > 0) {
       float* gin = bufs[l & 1];
-      hipLaunchKernelGGL(k_conv_bwd_x, dim3(HW / 256, CIN[l], batch), dim3(256), 0, s, g, COUT[l], w, CIN[l], gin);
+      hipLaunchKernelGGL(k_conv_bwd_x, dim3(HW / 256, CIN[l], batch), dim3(256), 0, s, g, COUT[l], w, CIN[l], DIL[l],
+                         gin);
       const size_t n = (size_t)batch * 32 * HW;
       hipLaunchKernelGGL(k_tanh_bwd, dim3(1024), dim3(256), 0, s, gin, acts + (size_t)batch * 32 * HW * (l - 1), n);
       g = gin;

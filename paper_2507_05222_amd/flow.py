@@ -14,22 +14,38 @@ from . import qtt as Q
 class FlowOps:
     """Operators (MPOs) and boundary vectors of a 2^n x 2^n O-grid (Sec. 3.2.3)."""
 
-    def __init__(self, n, r_out=20.0, Re=100.0, dt=1e-3, alpha=0.0, u_inf=1.0, device="cuda", order="interleaved"):
+    # operators that depend on the grid only (not on Re, dt, the wall rotation or u_inf)
+    GRID_ONLY = ("DX", "DZ", "DXP", "DZP", "WX", "WZ", "P", "JH", "JMH")
+
+    def __init__(self, n, r_out=20.0, Re=100.0, dt=1e-3, alpha=0.0, u_inf=1.0, device="cuda", order="interleaved",
+                 like=None):
+        """like: an FlowOps of the same grid (n, r_out, order) whose grid-only operators
+        are shared instead of rebuilt; the Helmholtz operator and the boundary vectors
+        are built for (Re, dt, alpha, u_inf)."""
         self.n, self.L = n, 2 * n
         self.order = order
         self.cyl = Q.cylinder(n, r_out, Re, dt, alpha, u_inf, order)
         names = ("DX", "DZ", "DXP", "DZP", "WX", "WZ", "HS", "P")
-        built = {k: Q.build_host(self.cyl, Q.OP[k]) for k in names}
+        if like is not None and (like.n, like.cyl.r_out, like.order) != (n, float(r_out), order):
+            raise ValueError("FlowOps(like=...): a different grid")
+        fresh = [k for k in names if like is None or k not in self.GRID_ONLY]
+        built = {k: Q.build_host(self.cyl, Q.OP[k]) for k in fresh}
         # operators applied in one batched call share one slot capacity
-        self.wcap = max(b[2] for b in built.values())
-        self.mpo = {k: Q.MPO(*Q.build_host(self.cyl, Q.OP[k], self.wcap)[:2], self.wcap, device) for k in names}
+        self.wcap = max([b[2] for b in built.values()] + ([like.wcap] if like is not None else []))
+        if like is not None and self.wcap != like.wcap:
+            raise ValueError("FlowOps(like=...): the Helmholtz operator needs another slot capacity")
+        self.mpo = {k: Q.MPO(_relayout(built[k][0], built[k][2], self.wcap, 4), built[k][1], self.wcap, device)
+                    for k in fresh}
+        for k in names:
+            if k not in self.mpo:
+                self.mpo[k] = like.mpo[k]
         for k in ("JH", "JMH"):
-            self.mpo[k] = Q.build_mpo(self.cyl, Q.OP[k], device)
-        caps = [Q.build_host(self.cyl, Q.VEC[k])[2] for k in
-                ("BX_U", "BZ_U", "BX_V", "BZ_V", "BL_U", "BL_V", "BW")]
-        self.bc_cap = max(caps)
-        self.vec = {k: Q.build_vec(self.cyl, Q.VEC[k], self.bc_cap, device) for k in
-                    ("BX_U", "BZ_U", "BX_V", "BZ_V", "BL_U", "BL_V", "BW")}
+            self.mpo[k] = like.mpo[k] if like is not None else Q.build_mpo(self.cyl, Q.OP[k], device)
+        vnames = ("BX_U", "BZ_U", "BX_V", "BZ_V", "BL_U", "BL_V", "BW")
+        bv = {k: Q.build_host(self.cyl, Q.VEC[k]) for k in vnames}
+        self.bc_cap = max(b[2] for b in bv.values())
+        self.vec = {k: Q.MPS.from_slots(_relayout(bv[k][0], bv[k][2], self.bc_cap, 2), bv[k][1], self.bc_cap, device)
+                    for k in vnames}
         m, v = self.mpo, self.vec
         self.c = Q.CFlowOps(m["DX"].desc(), m["DZ"].desc(), m["DXP"].desc(), m["DZP"].desc(), m["WX"].desc(),
                             m["WZ"].desc(), m["HS"].desc(), m["P"].desc(), m["JH"].desc(), m["JMH"].desc(),
@@ -38,6 +54,16 @@ class FlowOps:
 
     def bonds(self):
         return {k: int(max(m.bond_host)) for k, m in self.mpo.items()}
+
+
+def _relayout(slots, cap, cap_to, d):
+    """Slots of a train (L cores of cap x d x cap) copied into slots of cap_to >= cap."""
+    if cap == cap_to:
+        return slots
+    L = slots.size // (cap * d * cap)
+    out = np.zeros((L, cap_to, d, cap_to))
+    out[:, :cap, :, :cap] = slots.reshape(L, cap, d, cap)
+    return out.reshape(-1)
 
 
 class FlowState:

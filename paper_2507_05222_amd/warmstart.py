@@ -130,12 +130,15 @@ def save(path_json: str, params: np.ndarray, out_scale: float, extra: dict | Non
         json.dump(meta, f, indent=1)
 
 
-def compare_cold_learned(ctx: Q.Context, re: float, alpha: float, n=10, chi=64, dt=2e-3, history=3, tol=1e-8,
-                         ws: "WarmStart | None" = None):
-    """One fractional step of a developed state (history steps from uniform flow
-    plus the App. G perturbation) whose pressure guess is a seeded random train
-    (no previous pressure), solved to tol once cold and once with the learned
-    start. Returns per variant the step time, pressure sweeps and CG iterations."""
+def compare_starts(ctx: Q.Context, re: float, alpha: float, n=10, chi=64, dt=2e-3, history=24, tol=1e-8,
+                   ws: "WarmStart | None" = None, like=None):
+    """One fractional step of a flow `history` steps past uniform flow plus the App. G
+    perturbation, its pressure solved to `tol` from three starts: "cold" (a seeded
+    random train, no previous pressure), "learned" (the network's guess, rated by
+    the solve's energy against that random train) and "previous" (the previous
+    step's pressure, the start of a running simulation). Returns, per start, the
+    step time, the pressure sweeps and CG iterations, the residual and whether the
+    learned guess was taken. `like`: FlowOps of the same grid to share operators with."""
     import time
     from . import flow as F
     from qtt_inputs import random_mps_cores
@@ -144,9 +147,9 @@ def compare_cold_learned(ctx: Q.Context, re: float, alpha: float, n=10, chi=64, 
     i = np.arange(N)
     env = (np.exp((1.0 - (i + 1) / (N + 1)) ** 6) - 1.0) / (np.e - 1.0)
     u0 = 1.0 + 1e-2 * env[:, None] * np.sin(2 * np.pi * np.arange(N) / N)[None, :]
-    ops = F.FlowOps(n, 20.0, re, dt, alpha)
-    st = F.FlowState(Q.tt_svd_host(F.grid_to_qtt_order(u0), L, 1e-14, chi, chi),
-                     Q.tt_svd_host(np.zeros(N * N), L, 1e-14, chi, chi),
+    ops = F.FlowOps(n, 20.0, re, dt, alpha, like=like)
+    st = F.FlowState(Q.from_dense(ctx, F.grid_to_qtt_order(u0), L, 1e-14, chi, chi),
+                     Q.from_dense(ctx, np.zeros(N * N), L, 1e-14, chi, chi),
                      Q.MPS.from_cores(random_mps_cores(L, chi, seed=0), chi))
     so = Q.solve_opts(tol=tol, max_sweeps=12, max_local_iters=80, local_tol=1e-2, dtype="f64")
     plain = F.step_opts(dt, tol=1e-8, chi=chi, dtype="f64", pois=so)
@@ -155,9 +158,10 @@ def compare_cold_learned(ctx: Q.Context, re: float, alpha: float, n=10, chi=64, 
     ws = ws or WarmStart.load(ctx, re, alpha, chi=16, bf16=True)
     ws.re, ws.alpha = float(re), float(alpha)
     out = {}
-    for name, warm in (("cold", None), ("learned", ws)):
-        s = F.FlowState(Q.MPS(L, chi).copy_(st.u), Q.MPS(L, chi).copy_(st.v),
-                        Q.MPS.from_cores(random_mps_cores(L, chi, seed=7), chi))
+    for name, warm, p0 in (("cold", None, None), ("learned", ws, None), ("previous", None, st.p)):
+        p = Q.MPS(L, chi)
+        p.copy_(p0 if p0 is not None else Q.MPS.from_cores(random_mps_cores(L, chi, seed=7), chi))
+        s = F.FlowState(Q.MPS(L, chi).copy_(st.u), Q.MPS(L, chi).copy_(st.v), p)
         c2 = Q.Context(0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -166,4 +170,4 @@ def compare_cold_learned(ctx: Q.Context, re: float, alpha: float, n=10, chi=64, 
         out[name] = {"step_s": time.perf_counter() - t0, "sweeps": info.poisson.sweeps,
                      "cg_iters": info.poisson.local_iters, "residual": info.poisson.residual,
                      "warm_used": int(info.warm_used)}
-    return out
+    return out, ops
