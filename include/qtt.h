@@ -341,7 +341,8 @@ enum {
   QTT_OP_DX = 0, QTT_OP_DZ, QTT_OP_DXP, QTT_OP_DZP, QTT_OP_WX, QTT_OP_WZ,
   QTT_OP_HS, QTT_OP_P, QTT_OP_JH, QTT_OP_JMH, QTT_OP_LAP,
   QTT_VEC_BX_U = 100, QTT_VEC_BZ_U, QTT_VEC_BX_V, QTT_VEC_BZ_V, QTT_VEC_BL_U,
-  QTT_VEC_BL_V, QTT_VEC_BW, QTT_VEC_ABSJ
+  QTT_VEC_BL_V, QTT_VEC_BW, QTT_VEC_ABSJ,
+  QTT_VEC_MESH_X = 200, QTT_VEC_MESH_Z, QTT_VEC_JAC   /* qtt_build_tt only */
 };
 enum { QTT_ORDER_INTERLEAVED = 0, QTT_ORDER_CONCATENATED = 1 };
 typedef struct {
@@ -358,6 +359,39 @@ typedef struct {
 
 int qtt_build_host(const qtt_cylinder* cyl, int which, int32_t cap, double* out,
                    int32_t* bond_out, int32_t* need);
+
+/* The same operators built in TT format on the device (Sec. 3.2.2, Sec. 3.2.3),
+ * without forming any 2^n x 2^n field: the grid coordinates x, z as direct sums of
+ * an eta-train (ones, exponential wall-normal spacing) concatenated with a
+ * xi-train (wall curve, unit normal; encoded from their 2^n values), in the
+ * cylinder's bit order; metric terms by the computational central-difference
+ * MPOs D_xi, D_eta applied to x, z (the wall and far-field rows enter as boundary
+ * vectors); the Jacobian J = x_xi z_eta - x_eta z_xi by Hadamard products (each
+ * product formed exactly, then rounded by QR and Jacobi SVD sweeps); 1/J
+ * as the ALS solution of diag(-J) a = -1 (qtt_poisson_solve; J < 0 on this grid),
+ * polished by Newton steps a <- a + a (1 - J a) (eight at most) down to
+ * ||1 - J a|| / ||1|| of some 1e-13;
+ * D_x = C1 D_xi - C2 D_eta with C1 = diag(z_eta / J), C2 = diag(z_xi / J) by
+ * MPO products, D_z likewise; the seven-term Laplacian of App. A from the metric
+ * tensor (Hadamard products) and the eta / xi differences of g_kl / J; the pressure
+ * variants fold the wall-row neighbours into row 0 (p_{-1} = p_0), W = -|J| D and
+ * P = -|J| Lap_p. Every field operation drops what lies below 1e-14 of its
+ * result's norm at each bond, every operator sum or product below 1e-13; a sum
+ * that cancels below 1e-12 of its operands' scale (g12 and the xi-derivatives of an
+ * orthogonal grid) is taken as exactly zero.
+ *
+ * which: QTT_OP_DX, QTT_OP_DZ, QTT_OP_DXP, QTT_OP_DZP, QTT_OP_WX, QTT_OP_WZ,
+ * QTT_OP_LAP, QTT_OP_P (an
+ * MPO: `out` DEVICE double[L*cap*4*cap] in slot layout, `bond_out` DEVICE
+ * int32[L+1], `bond_host` HOST int32[L+1]) or QTT_VEC_MESH_X, QTT_VEC_MESH_Z,
+ * QTT_VEC_JAC (an MPS: `out` DEVICE double[L*cap*2*cap]). With out == NULL only
+ * the needed capacity is returned in *need (HOST, may be NULL otherwise); the
+ * object is built either way. QTT_ECAPACITY if cap is too small,
+ * QTT_ENOTCONVERGED if the inverse Jacobian stalls above 1e-12.
+ * Allocates its temporaries (setup only) and synchronises `stream`. Requires
+ * 2 <= n <= 13. */
+int qtt_build_tt(qtt_ctx* ctx, const qtt_cylinder* cyl, int which, int32_t cap, double* out,
+                 int32_t* bond_out, int32_t* bond_host, int32_t* need, void* stream);
 
 /* ---- diagnostics (Sec. 4, App. C, App. F) --------------------------------- */
 

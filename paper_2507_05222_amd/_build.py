@@ -8,7 +8,7 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libqtt.so")
-SOURCES = ["kernels.hip", "api.hip", "solve.hip", "fit.hip", "step.hip", "wsnet.hip", "diag.hip", "builder.cpp", "host_linalg.cpp"]
+SOURCES = ["kernels.hip", "api.hip", "solve.hip", "fit.hip", "step.hip", "wsnet.hip", "diag.hip", "ttbuild.hip", "builder.cpp", "host_linalg.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -601,6 +601,7 @@ void set_step_warm(qtt_ctx* ctx, uint64_t gen, const void* const id[3], int L, i
   for (int i = 0; i < 3; ++i) ctx->step_warm_id[i] = id[i];
 }
 int lds_of(qtt_ctx* ctx) { return ctx->lds; }
+int device_of(qtt_ctx* ctx) { return ctx->device; }
 int coop_of(qtt_ctx* ctx) { return ctx->coop; }
 double* pinned(qtt_ctx* ctx, size_t doubles, int* rc) {
   *rc = ensure_pinned(ctx, doubles);

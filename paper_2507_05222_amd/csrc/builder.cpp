@@ -22,6 +22,7 @@
 
 #include "../../include/qtt.h"
 #include "host_linalg.h"
+#include "cylinder_parts.h"
 
 namespace {
 
@@ -356,6 +357,20 @@ int write_mps(const HostTT& T, int32_t cap, double* out, int32_t* bond_out, int3
 }
 
 }  // namespace
+
+// ---- pieces the TT-format construction (ttbuild.hip) shares ------------------
+HostTT cyl_shift_mpo(int n, int di, int dj, int order) {
+  const int saved = t_order;
+  t_order = order;
+  HostTT T = shift_mpo(n, di, dj);
+  t_order = saved;
+  return T;
+}
+
+double cyl_row_radius(int i, int n, double r_out) {
+  const int N = 1 << n;
+  return 0.5 * std::pow(2.0 * r_out, (i + 1) * (1.0 / (N + 1)));
+}
 
 extern "C" int qtt_build_host(const qtt_cylinder* cyl, int which, int32_t cap, double* out,
                               int32_t* bond_out, int32_t* need) {

@@ -1,5 +1,5 @@
 """Flow-level helpers of the binding: build the cylinder operators with the
-library's host builder, hold the GPU state (u, v, p) and call the fractional step.
+library's host builder (or its TT-format builder), hold the GPU state (u, v, p) and call the fractional step.
 Marshalling only; all arithmetic runs in libqtt.so."""
 from __future__ import annotations
 
@@ -18,10 +18,15 @@ class FlowOps:
     GRID_ONLY = ("DX", "DZ", "DXP", "DZP", "WX", "WZ", "P", "JH", "JMH")
 
     def __init__(self, n, r_out=20.0, Re=100.0, dt=1e-3, alpha=0.0, u_inf=1.0, device="cuda", order="interleaved",
-                 like=None):
+                 like=None, construction="host", ctx=None):
         """like: an FlowOps of the same grid (n, r_out, order) whose grid-only operators
         are shared instead of rebuilt; the Helmholtz operator and the boundary vectors
-        are built for (Re, dt, alpha, u_inf)."""
+        are built for (Re, dt, alpha, u_inf).
+        construction: "host" (every operator from qtt_build_host) or "tt" (the first
+        derivatives, their pressure and |J|-weighted forms and the pressure operator built
+        in TT format on the device by qtt_build_tt, Sec. 3.2.3; needs ctx)."""
+        if construction not in ("host", "tt") or (construction == "tt" and ctx is None):
+            raise ValueError("FlowOps: construction is 'host' or 'tt' (with ctx)")
         self.n, self.L = n, 2 * n
         self.order = order
         self.cyl = Q.cylinder(n, r_out, Re, dt, alpha, u_inf, order)
@@ -29,7 +34,8 @@ class FlowOps:
         if like is not None and (like.n, like.cyl.r_out, like.order) != (n, float(r_out), order):
             raise ValueError("FlowOps(like=...): a different grid")
         fresh = [k for k in names if like is None or k not in self.GRID_ONLY]
-        built = {k: Q.build_host(self.cyl, Q.OP[k]) for k in fresh}
+        built = {k: (self._tt(ctx, k) if construction == "tt" and k in Q.TT_OPS else Q.build_host(self.cyl, Q.OP[k]))
+                 for k in fresh}
         # operators applied in one batched call share one slot capacity
         self.wcap = max([b[2] for b in built.values()] + ([like.wcap] if like is not None else []))
         if like is not None and self.wcap != like.wcap:
@@ -51,6 +57,10 @@ class FlowOps:
                             m["WZ"].desc(), m["HS"].desc(), m["P"].desc(), m["JH"].desc(), m["JMH"].desc(),
                             v["BX_U"].desc(), v["BZ_U"].desc(), v["BX_V"].desc(), v["BZ_V"].desc(),
                             v["BL_U"].desc(), v["BL_V"].desc(), v["BW"].desc())
+
+    def _tt(self, ctx, k):
+        m = Q.build_tt(ctx, self.cyl, Q.OP[k])
+        return m.data.cpu().numpy(), m.bond_host.copy(), m.wcap
 
     def bonds(self):
         return {k: int(max(m.bond_host)) for k, m in self.mpo.items()}

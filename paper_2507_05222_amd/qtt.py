@@ -21,6 +21,8 @@ DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
 
 OP = dict(DX=0, DZ=1, DXP=2, DZP=3, WX=4, WZ=5, HS=6, P=7, JH=8, JMH=9, LAP=10)
 VEC = dict(BX_U=100, BZ_U=101, BX_V=102, BZ_V=103, BL_U=104, BL_V=105, BW=106, ABSJ=107)
+TT_VEC = dict(MESH_X=200, MESH_Z=201, JAC=202)   # objects only qtt_build_tt makes
+TT_OPS = ("DX", "DZ", "DXP", "DZP", "WX", "WZ", "LAP", "P")  # operators qtt_build_tt makes
 
 ERRORS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ECAPACITY", -4: "ENUMERIC", -5: "ENOTCONVERGED", -6: "EHIP"}
 
@@ -127,6 +129,7 @@ def lib():
                                      p(ctypes.c_double), p(ctypes.c_double)]
         L.qtt_timer_durations.argtypes = [vp, p(ctypes.c_double), ctypes.c_int64, p(ctypes.c_int64)]
         L.qtt_build_host.argtypes = [p(CCylinder), i32, ctypes.c_int32, vp, vp, p(ctypes.c_int32)]
+        L.qtt_build_tt.argtypes = [vp, p(CCylinder), i32, ctypes.c_int32, vp, vp, vp, p(ctypes.c_int32), vp]
         L.qtt_tt_svd_host.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, p(CTrunc), ctypes.c_int32, vp, vp]
         L.qtt_from_dense.argtypes = [vp, vp, ctypes.c_int32, p(CTrunc), p(CMps), vp]
         L.qtt_strouhal_host.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
@@ -245,6 +248,10 @@ class MPO:
 
     def desc(self) -> CMpo:
         return CMpo(self.L, self.wcap, self.bond_host.ctypes.data, self.bond.data_ptr(), self.data.data_ptr())
+
+    @classmethod
+    def empty(cls, L: int, wcap: int, device="cuda"):
+        return cls(np.zeros(L * wcap * 4 * wcap), np.ones(L + 1, dtype=np.int32), wcap, device)
 
     @classmethod
     def from_cores(cls, cores: Sequence[np.ndarray], wcap: int | None = None, device="cuda"):
@@ -392,6 +399,26 @@ def build_host(cyl: CCylinder, which: int, cap: int | None = None):
     if rc != 0:
         raise QttError(rc, "qtt_build_host")
     return slots, bonds, cap
+
+
+def build_tt(ctx: "Context", cyl: CCylinder, which: int, cap: int | None = None, stream=None):
+    """An operator (QTT_OP_* in TT_OPS: an MPO) or a mesh field (TT_VEC: an MPS) built
+    in TT format on the device by qtt_build_tt."""
+    need = ctypes.c_int32(0)
+    st = _stream(stream)
+    ctx.check(lib().qtt_build_tt(ctx.h, ctypes.byref(cyl), int(which), 0, None, None, None, ctypes.byref(need), st))
+    cap = max(cap or 0, need.value)
+    L = 2 * cyl.n
+    if which >= 100:
+        m = MPS(L, cap)
+        bh = np.zeros(L + 1, dtype=np.int32)
+        ctx.check(lib().qtt_build_tt(ctx.h, ctypes.byref(cyl), int(which), cap, m.data.data_ptr(),
+                                     m.bond.data_ptr(), bh.ctypes.data, None, st))
+        return m
+    m = MPO.empty(L, cap)
+    ctx.check(lib().qtt_build_tt(ctx.h, ctypes.byref(cyl), int(which), cap, m.data.data_ptr(), m.bond.data_ptr(),
+                                 m.bond_host.ctypes.data, None, st))
+    return m
 
 
 def build_mpo(cyl: CCylinder, which: int, device="cuda") -> MPO:

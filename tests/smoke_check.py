@@ -26,12 +26,12 @@ def c1_initial(n=5, chi=8, tol=1e-10, order="interleaved"):
 
 
 def run_c1(cap=32, n=5, Re=100.0, dt=1e-3, trunc_tol=1e-13, dtype="f64", helm_dtype=None, pois_dtype=None,
-           product_dtype=None, order="interleaved", alpha=0.0):
+           product_dtype=None, order="interleaved", alpha=0.0, construction="host"):
     from paper_2507_05222_amd import flow as F, qtt as Q
     L = 2 * n
     ctx = Q.Context(0)
     (u0, mu), (v0, mv) = c1_initial(n, order=order)
-    ops = F.FlowOps(n, 20.0, Re, dt, alpha, order=order)
+    ops = F.FlowOps(n, 20.0, Re, dt, alpha, order=order, construction=construction, ctx=ctx)
     u = Q.MPS(L, cap); v = Q.MPS(L, cap)
     Q.add(ctx, 1.0, [mu], 0.0, [mu], [u], tol=0.0, chi=cap)
     Q.add(ctx, 1.0, [mv], 0.0, [mv], [v], tol=0.0, chi=cap)
