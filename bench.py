@@ -269,7 +269,7 @@ def steady(args):
     import torch
     from paper_2507_05222_amd import diag as D, flow as F, qtt as Q
     from qtt_inputs import random_mps_cores
-    n, chi, Re, dt, K = 8, 32, 40.0, 5e-3, args.steady_steps
+    n, chi, Re, dt, K = 8, args.steady_chi, 40.0, 5e-3, args.steady_steps
     L = 2 * n
     ctx = Q.Context(0)
     ops = F.FlowOps(n, 20.0, Re, dt)
@@ -277,6 +277,8 @@ def steady(args):
     so = lambda tol: Q.solve_opts(tol=tol, max_sweeps=8, max_local_iters=80, local_tol=1e-2, dtype="f64")
     res = {}
     for name, dtype in (("fp64", "f64"), ("fp32", "f32")):
+        if name not in args.steady_paths.split(","):
+            continue
         st = F.FlowState(Q.tt_svd_host(F.grid_to_qtt_order(u0), L, 1e-14, chi, chi),
                          Q.tt_svd_host(F.grid_to_qtt_order(v0), L, 1e-14, chi, chi),
                          Q.MPS.from_cores(random_mps_cores(L, chi, seed=0), chi))
@@ -414,6 +416,8 @@ def main():
     ap.add_argument("--steady", action="store_true",
                     help="steady cylinder Re=40 on 2^8 x 2^8, chi 32: FP64 vs FP32-MFMA contractions, forces vs the oracle")
     ap.add_argument("--steady-steps", type=int, default=2000)
+    ap.add_argument("--steady-chi", type=int, default=32, help="bond of the --steady run")
+    ap.add_argument("--steady-paths", default="fp64,fp32", help="paths of the --steady run (fp64, fp32)")
     ap.add_argument("--shedding", action="store_true",
                     help="long transient run (--case c3 or rotating_g1) on the FP64 path, forces every 10 steps, resumable")
     ap.add_argument("--shedding-steps", type=int, default=20000)

@@ -11,6 +11,8 @@ MFMA contractions, both tile sizes).
 
   python -m paper_2507_05222_amd.profile_summary --fetch F.db --write W.db \\
       --cal-fetch CF.db --cal-write CW.db --trace T.db --out profiles/....json [--kernel cg_coop]
+
+`--table T.db [N]` prints the N largest kernels of a kernel-trace database instead.
 """
 from __future__ import annotations
 
@@ -56,7 +58,35 @@ def source_hash(files):
     return h.hexdigest()[:16]
 
 
+def short_name(name):
+    """A kernel's name without its return type, namespace and parameter list."""
+    name = name.replace("(anonymous namespace)::", "")
+    if name.startswith("void "):
+        name = name[5:]
+    return name.split("(")[0][:70]
+
+
+def kernel_table(db, top=25):
+    """Markdown rows (name, launches, total ms, mean us, share of kernel time) of a
+    kernel-trace database, largest total first."""
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, count(*), sum(end - start), avg(end - start) from kernels group by name "
+                     "order by sum(end - start) desc").fetchall()
+    tot = sum(r[2] for r in rows)
+    lo, hi = c.execute("select min(start), max(end) from kernels").fetchone()
+    out = [f"kernel time {tot / 1e6:.1f} ms over a span of {(hi - lo) / 1e6:.1f} ms, "
+           f"{sum(r[1] for r in rows)} launches", "",
+           "| kernel | launches | total ms | mean us | share |", "|---|---:|---:|---:|---:|"]
+    for n, cnt, s, a in rows[:top]:
+        out.append(f"| `{short_name(n)}` | {cnt} | {s / 1e6:.1f} | {a / 1e3:.1f} | {100 * s / tot:.1f}% |")
+    return "\n".join(out)
+
+
 def main():
+    import sys
+    if len(sys.argv) >= 3 and sys.argv[1] == "--table":
+        print(kernel_table(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 25))
+        return
     ap = argparse.ArgumentParser()
     for a in ("fetch", "write", "cal_fetch", "cal_write", "trace", "out"):
         ap.add_argument("--" + a.replace("_", "-"), required=True)
