@@ -191,9 +191,10 @@ CASES = {
 
 
 def shedding(args):
-    """A long transient run on the FP64 path (--case: "c3", the 2^10 x 2^10 transient
-    cylinder, or "rotating_g1", the paper's rotating cylinder of Table 2; --chi
-    overrides the case's bond), drag and lift every 10 steps, resumable: the TT
+    """A long transient run (--case: "c3", the 2^10 x 2^10 transient cylinder, or
+    "rotating_g1", the paper's rotating cylinder of Table 2; --chi-case overrides the
+    case's bond; FP64 throughout, or with --shedding-product f32 the mixed path's FP32
+    Hadamard products), drag and lift every 10 steps, resumable: the TT
     state, the step count and the force history go to --ckpt-out after every 1000
     steps and are read from --ckpt-in if given. Once --shedding-steps are done the
     Strouhal number, lift amplitude and mean lift (upward zero crossings of C_L, last
@@ -209,7 +210,8 @@ def shedding(args):
     ctx = Q.Context(0)
     ops = F.FlowOps(n, c["r_out"], Re, dt, c["alpha"])
     so = lambda tol, sw: Q.solve_opts(tol=tol, max_sweeps=sw, max_local_iters=80, local_tol=args.local_tol, dtype="f64")
-    opts = F.step_opts(dt, tol=1e-8, chi=chi, dtype="f64", product="f64", helm=so(1e-8, 4), pois=so(args.pois_tol, 8))
+    opts = F.step_opts(dt, tol=1e-8, chi=chi, dtype="f64", product=args.shedding_product, helm=so(1e-8, 4),
+                       pois=so(args.pois_tol, 8))
     st = F.FlowState(Q.MPS(L, chi), Q.MPS(L, chi), Q.MPS(L, chi))
     if args.ckpt_in and os.path.exists(args.ckpt_in):
         z = np.load(args.ckpt_in, allow_pickle=False)
@@ -426,6 +428,8 @@ def main():
     ap.add_argument("--steps-per-call", type=int, default=20000)
     ap.add_argument("--ckpt-in", default=None)
     ap.add_argument("--ckpt-out", default=None)
+    ap.add_argument("--shedding-product", default="f64", choices=["f64", "f32", "bf16"],
+                    help="MFMA type of the Hadamard products of the --shedding run")
     ap.add_argument("--pois-tol", type=float, default=1e-8, help="pressure tolerance of the --shedding run")
     args = ap.parse_args()
     if args.gpus != 1:
