@@ -162,6 +162,44 @@ __global__ void k_precond(SBatch sb, SGeo g, SLay l) {
   }
 }
 
+// The same diagonal factored through the MPO bond b' (MPO bonds <= 32, capacity <= 64):
+// T[(a, s)][b'] = sum_b LA[a][b][a] A[b][s][s][b'], then diag = sum_b' T[(a, s)][b'] RA[c][b'][c]
+// (w w' + w' per element instead of w w'); each of the gridDim.x workgroups of a chain
+// forms T in LDS and takes its share of the elements.
+constexpr int PD_W = 32, PD_C = 64;
+__global__ void __launch_bounds__(256) k_precond_fact(SBatch sb, SGeo g, SLay l) {
+  __shared__ double T[2 * PD_C][PD_W + 1];
+  __shared__ double RAd[PD_C][PD_W + 1];
+  if (blockIdx.y >= sb.n) return;
+  const SChain& c = sb.c[blockIdx.y];
+  const int k = g.k, cx = g.cx;
+  const int nl = c.xb[k], nr = c.xb[k + 1], w = c.ab[k], w2 = c.ab[k + 1];
+  const double* LA = c.ws + l.LA + (size_t)k * l.env;
+  const double* RA = c.ws + l.RA + (size_t)(k + 1) * l.env;
+  const double* Ak = c.A + (long)k * g.wcap * 4 * g.wcap;
+  double* dinv = c.ws + l.dinv;
+  for (int e = threadIdx.x; e < 2 * PD_C * PD_W; e += blockDim.x) {
+    const int row = e / PD_W, b2 = e % PD_W, a = row >> 1, s = row & 1;
+    double v = 0.0;
+    if (a < nl && b2 < w2)
+      for (int b = 0; b < w; ++b)
+        v += LA[((size_t)a * w + b) * cx + a] * Ak[(long)b * 4 * g.wcap + s * 2 * g.wcap + s * g.wcap + b2];
+    T[row][b2] = v;
+  }
+  for (int e = threadIdx.x; e < PD_C * PD_W; e += blockDim.x) {
+    const int cc = e / PD_W, b2 = e % PD_W;
+    RAd[cc][b2] = (cc < nr && b2 < w2) ? RA[((size_t)cc * w2 + b2) * cx + cc] : 0.0;
+  }
+  __syncthreads();
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 2 * cx * cx; e += gridDim.x * blockDim.x) {
+    const int a = e / (2 * cx), s = (e / cx) % 2, cc = e % cx;
+    double v = 0.0;
+    if (a < nl && cc < nr)
+      for (int b2 = 0; b2 < w2; ++b2) v += T[2 * a + s][b2] * RAd[cc][b2];
+    dinv[e] = v > 0.0 ? 1.0 / v : 1.0;
+  }
+}
+
 // Local CG (one workgroup per chain): vectors in [a][s][c] layout with row
 // stride cx; the unknown is core k of x itself.
 __device__ double block_sum(double v, double* red) {
@@ -985,7 +1023,8 @@ struct Solver {
     gg.k = k;
     beff(k);
     build_lm(k);
-    hipLaunchKernelGGL(k_precond, dim3(8, sb.n), dim3(256), 0, s, sb, gg, l);
+    if (g.W <= PD_W && g.cx <= PD_C) hipLaunchKernelGGL(k_precond_fact, dim3(8, sb.n), dim3(256), 0, s, sb, gg, l);
+    else hipLaunchKernelGGL(k_precond, dim3(8, sb.n), dim3(256), 0, s, sb, gg, l);
     if (mmode == 0 && coopG > 0) {
       int first = 1, G = coopG;
       double* cnt = nullptr;
