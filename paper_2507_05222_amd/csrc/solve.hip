@@ -442,6 +442,70 @@ __device__ __forceinline__ void pc_bsum3(double& a, double& b, double& c, double
   for (int w = 0; w < PC_THREADS / 64; ++w) { a += red[0][w]; b += red[1][w]; c += red[2][w]; }
 }
 
+// Two 16 x 16 FP64 MFMA tiles sharing their A operand: acc0 += A B0, acc1 += A B1 over
+// K (a multiple of 4), A read at a[kk] (row of the lane's tile row, step `as` per k),
+// B0 at b[kk * ldb] and B1 sixteen columns further. The K loop runs in blocks of 16:
+// all twelve LDS reads of a block are issued before its MFMAs, and even and odd
+// k-steps accumulate separately (two chains per tile), summed at the end.
+__device__ __forceinline__ void mfma_pair(const double* a, int as, const double* b, int ldb, int K, v4d& acc0,
+                                          v4d& acc1) {
+  v4d e0 = {0, 0, 0, 0}, e1 = {0, 0, 0, 0}, o0 = {0, 0, 0, 0}, o1 = {0, 0, 0, 0};
+  int kk = 0;
+  for (; kk + 16 <= K; kk += 16) {
+    double av[4], b0[4], b1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      av[u] = a[(kk + 4 * u) * as];
+      b0[u] = b[(kk + 4 * u) * ldb];
+      b1[u] = b[(kk + 4 * u) * ldb + 16];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u += 2) {
+      e0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], b0[u], e0, 0, 0, 0);
+      e1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], b1[u], e1, 0, 0, 0);
+      o0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u + 1], b0[u + 1], o0, 0, 0, 0);
+      o1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u + 1], b1[u + 1], o1, 0, 0, 0);
+    }
+  }
+  for (; kk < K; kk += 4) {
+    const double av = a[kk * as], b0 = b[kk * ldb], b1 = b[kk * ldb + 16];
+    e0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, e0, 0, 0, 0);
+    e1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, e1, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) { acc0[v] = e0[v] + o0[v]; acc1[v] = e1[v] + o1[v]; }
+}
+// The same with B stored transposed (consecutive k contiguous): B0 of the lane at
+// b[kk], B1 at b[boff + kk].
+__device__ __forceinline__ void mfma_pair_t(const double* a, const double* b, int boff, int K, v4d& acc0,
+                                            v4d& acc1) {
+  v4d e0 = {0, 0, 0, 0}, e1 = {0, 0, 0, 0}, o0 = {0, 0, 0, 0}, o1 = {0, 0, 0, 0};
+  int kk = 0;
+  for (; kk + 16 <= K; kk += 16) {
+    double av[4], b0[4], b1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      av[u] = a[kk + 4 * u];
+      b0[u] = b[kk + 4 * u];
+      b1[u] = b[boff + kk + 4 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u += 2) {
+      e0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], b0[u], e0, 0, 0, 0);
+      e1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], b1[u], e1, 0, 0, 0);
+      o0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u + 1], b0[u + 1], o0, 0, 0, 0);
+      o1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u + 1], b1[u + 1], o1, 0, 0, 0);
+    }
+  }
+  for (; kk < K; kk += 4) {
+    const double av = a[kk], b0 = b[kk], b1 = b[boff + kk];
+    e0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, e0, 0, 0, 0);
+    e1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, e1, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) { acc0[v] = e0[v] + o0[v]; acc1[v] = e1[v] + o1[v]; }
+}
+
 __global__ void __launch_bounds__(PC_THREADS) k_cg_coop(SBatch sb, SGeo g, SLay l, int G, int first, double* cnt) {
   extern __shared__ double smem[];
   double* LMs = smem;                               // [PC_RB][PC_LDL]   rows of LM_{b'} of this unit
@@ -533,15 +597,8 @@ __global__ void __launch_bounds__(PC_THREADS) k_cg_coop(SBatch sb, SGeo g, SLay 
     }
     __syncthreads();
     if (unit) {
-      v4d a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
-      const int K1 = (2 * nl + 3) & ~3;
-      for (int kk = 0; kk < K1; kk += 4) {
-        const double av = LMs[(r0 + li) * PC_LDL + kk + lk];
-        const double b0 = Us[(kk + lk) * PC_LDU + c0 + li];
-        const double b1 = Us[(kk + lk) * PC_LDU + c0 + 16 + li];
-        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, a0, 0, 0, 0);
-        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, a1, 0, 0, 0);
-      }
+      v4d a0, a1;
+      mfma_pair(LMs + (r0 + li) * PC_LDL + lk, 1, Us + lk * PC_LDU + c0 + li, PC_LDU, (2 * nl + 3) & ~3, a0, a1);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         Ts[(r0 + lk + 4 * v) * PC_LDT + c0 + li] = a0[v];
@@ -550,15 +607,8 @@ __global__ void __launch_bounds__(PC_THREADS) k_cg_coop(SBatch sb, SGeo g, SLay 
     }
     __syncthreads();
     if (unit) {
-      v4d a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
-      const int K2 = (nr + 3) & ~3;
-      for (int kk = 0; kk < K2; kk += 4) {
-        const double av = Ts[(r0 + li) * PC_LDT + kk + lk];
-        const double b0 = RAs[(c0 + li) * PC_LDR + kk + lk];
-        const double b1 = RAs[(c0 + 16 + li) * PC_LDR + kk + lk];
-        a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, a0, 0, 0, 0);
-        a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, a1, 0, 0, 0);
-      }
+      v4d a0, a1;
+      mfma_pair_t(Ts + (r0 + li) * PC_LDT + lk, RAs + (c0 + li) * PC_LDR + lk, 16 * PC_LDR, (nr + 3) & ~3, a0, a1);
       double* Pb = P + (long)bp * n;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
