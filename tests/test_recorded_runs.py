@@ -1,7 +1,8 @@
-"""The recorded TT run of the rotating cylinder (Sec. 4.2, Table 2: G1, Re = 100, rotation
-rate 1, chi = 40, t = 0 .. 40; written by the library on the GPU, results/) against the
-oracle's FD history of the same case over the same window, and against the TT row of
-Table 2 for chi = 40. CPU only: checks the committed record, not the GPU."""
+"""The recorded TT runs (written by the library on the GPU, results/) against the oracle's
+FD histories of the same cases: the rotating cylinder of Sec. 4.2 (Table 2: G1, Re = 100,
+rotation rate 1, chi = 40, t = 0 .. 40), also against the TT row of Table 2 for chi = 40,
+and the 2^10 x 2^10 transient cylinder at Re = 200 (chi = 64, mixed path, t = 0 .. 40).
+CPU only: checks the committed records, not the GPU."""
 import json
 import os
 
@@ -47,3 +48,30 @@ def test_tt_rotating_cylinder_matches_fd_and_table2():
     # the whole drag and lift histories: relative L2 differences of about 1%
     assert np.linalg.norm(tt[:, 1] - fd[:, 1]) <= 0.03 * np.linalg.norm(fd[:, 1])
     assert np.linalg.norm(tt[:, 2] - fd[:, 2]) <= 0.03 * np.linalg.norm(fd[:, 2])
+
+
+def _crossings(t, y):
+    """Upward zero crossings of y - mean(y), linearly interpolated."""
+    y = y - y.mean()
+    i = np.where((y[:-1] < 0) & (y[1:] >= 0))[0]
+    return t[i] - y[i] * (t[i + 1] - t[i]) / (y[i + 1] - y[i])
+
+
+def test_tt_transient_cylinder_matches_fd():
+    """2^10 x 2^10, Re = 200, chi = 64, mixed path: over the last half (t = 20 .. 40) the
+    Strouhal number from the lift's upward crossings, the lift amplitude and the mean drag
+    agree with the oracle's FD run, and the whole histories stay within the 3e-3 band."""
+    tt = np.loadtxt(os.path.join(ROOT, "results", "c3_re200_chi64_mixed_tt_forces.txt"))
+    fd = np.loadtxt(os.path.join(ROOT, "tests", "golden", "c3_re200_forces.txt"))
+    assert int(tt[-1, 0]) == 20000 and np.array_equal(tt[:, 0], fd[:, 0])
+    t = tt[:, 0] * DT
+    w = t >= 20.0
+    ct, cf = _crossings(t[w], tt[w, 2]), _crossings(t[w], fd[w, 2])
+    assert len(ct) == len(cf) >= 3 and np.abs(ct - cf).max() < 5e-3, (ct, cf)
+    st_tt, st_fd = (len(ct) - 1) / (ct[-1] - ct[0]), (len(cf) - 1) / (cf[-1] - cf[0])
+    assert abs(st_tt - st_fd) <= 1e-3 * st_fd, (st_tt, st_fd)
+    amp_tt, amp_fd = np.ptp(tt[w, 2]) / 2, np.ptp(fd[w, 2]) / 2
+    assert abs(amp_tt - amp_fd) <= 3e-3 * amp_fd, (amp_tt, amp_fd)
+    assert abs(tt[w, 1].mean() - fd[w, 1].mean()) <= 1e-3 * fd[w, 1].mean()
+    assert np.linalg.norm(tt[:, 1] - fd[:, 1]) <= 3e-3 * np.linalg.norm(fd[:, 1])
+    assert np.linalg.norm(tt[:, 2] - fd[:, 2]) <= 5e-3 * np.linalg.norm(fd[:, 2])
