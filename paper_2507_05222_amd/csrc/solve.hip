@@ -164,12 +164,15 @@ __global__ void k_precond(SBatch sb, SGeo g, SLay l) {
 
 // The same diagonal factored through the MPO bond b' (MPO bonds <= 32, capacity <= 64):
 // T[(a, s)][b'] = sum_b LA[a][b][a] A[b][s][s][b'], then diag = sum_b' T[(a, s)][b'] RA[c][b'][c]
-// (w w' + w' per element instead of w w'); each of the gridDim.x workgroups of a chain
-// forms T in LDS and takes its share of the elements.
-constexpr int PD_W = 32, PD_C = 64;
+// (w w' + w' per element instead of w w'). Workgroup x takes the PD_RB rows (a, s) from
+// x PD_RB on, all columns c; the diagonals of LA, A and RA it needs are staged into LDS
+// with all loads in flight first.
+constexpr int PD_W = 32, PD_C = 64, PD_RB = 16;
 __global__ void __launch_bounds__(256) k_precond_fact(SBatch sb, SGeo g, SLay l) {
-  __shared__ double T[2 * PD_C][PD_W + 1];
+  __shared__ double Ad[PD_W][2][PD_W + 1];
   __shared__ double RAd[PD_C][PD_W + 1];
+  __shared__ double LAd[PD_RB / 2][PD_W + 1];
+  __shared__ double T[PD_RB][PD_W + 1];
   if (blockIdx.y >= sb.n) return;
   const SChain& c = sb.c[blockIdx.y];
   const int k = g.k, cx = g.cx;
@@ -178,25 +181,34 @@ __global__ void __launch_bounds__(256) k_precond_fact(SBatch sb, SGeo g, SLay l)
   const double* RA = c.ws + l.RA + (size_t)(k + 1) * l.env;
   const double* Ak = c.A + (long)k * g.wcap * 4 * g.wcap;
   double* dinv = c.ws + l.dinv;
-  for (int e = threadIdx.x; e < 2 * PD_C * PD_W; e += blockDim.x) {
-    const int row = e / PD_W, b2 = e % PD_W, a = row >> 1, s = row & 1;
+  const int r0 = blockIdx.x * PD_RB, a0 = r0 / 2;
+  stage8(w * 2 * w2, [&](int e) {
+    const int b = e / (2 * w2), s = (e / w2) % 2, b2 = e % w2;
+    return Ak[(long)b * 4 * g.wcap + s * 2 * g.wcap + s * g.wcap + b2];
+  }, [&](int e, double v) { Ad[e / (2 * w2)][(e / w2) % 2][e % w2] = v; });
+  stage8(nr * w2, [&](int e) {
+    const int cc = e / w2, b2 = e % w2;
+    return RA[((size_t)cc * w2 + b2) * cx + cc];
+  }, [&](int e, double v) { RAd[e / w2][e % w2] = v; });
+  stage8((PD_RB / 2) * w, [&](int e) {
+    const int i = e / w, b = e % w, a = a0 + i;
+    return a < nl ? LA[((size_t)a * w + b) * cx + a] : 0.0;
+  }, [&](int e, double v) { LAd[e / w][e % w] = v; });
+  __syncthreads();
+  for (int e = threadIdx.x; e < PD_RB * w2; e += blockDim.x) {
+    const int i = e / w2, b2 = e % w2, s = i & 1;
     double v = 0.0;
-    if (a < nl && b2 < w2)
-      for (int b = 0; b < w; ++b)
-        v += LA[((size_t)a * w + b) * cx + a] * Ak[(long)b * 4 * g.wcap + s * 2 * g.wcap + s * g.wcap + b2];
-    T[row][b2] = v;
-  }
-  for (int e = threadIdx.x; e < PD_C * PD_W; e += blockDim.x) {
-    const int cc = e / PD_W, b2 = e % PD_W;
-    RAd[cc][b2] = (cc < nr && b2 < w2) ? RA[((size_t)cc * w2 + b2) * cx + cc] : 0.0;
+    for (int b = 0; b < w; ++b) v += LAd[i >> 1][b] * Ad[b][s][b2];
+    T[i][b2] = v;
   }
   __syncthreads();
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 2 * cx * cx; e += gridDim.x * blockDim.x) {
-    const int a = e / (2 * cx), s = (e / cx) % 2, cc = e % cx;
+  for (int e = threadIdx.x; e < PD_RB * cx; e += blockDim.x) {
+    const int i = e / cx, cc = e % cx, row = r0 + i;
+    if (row >= 2 * cx) continue;
     double v = 0.0;
-    if (a < nl && cc < nr)
-      for (int b2 = 0; b2 < w2; ++b2) v += T[2 * a + s][b2] * RAd[cc][b2];
-    dinv[e] = v > 0.0 ? 1.0 / v : 1.0;
+    if ((row >> 1) < nl && cc < nr)
+      for (int b2 = 0; b2 < w2; ++b2) v += T[i][b2] * RAd[cc][b2];
+    dinv[(size_t)row * cx + cc] = v > 0.0 ? 1.0 / v : 1.0;
   }
 }
 
@@ -1073,7 +1085,8 @@ struct Solver {
     gg.k = k;
     beff(k);
     build_lm(k);
-    if (g.W <= PD_W && g.cx <= PD_C) hipLaunchKernelGGL(k_precond_fact, dim3(8, sb.n), dim3(256), 0, s, sb, gg, l);
+    if (g.W <= PD_W && g.cx <= PD_C)
+      hipLaunchKernelGGL(k_precond_fact, dim3((2 * g.cx + PD_RB - 1) / PD_RB, sb.n), dim3(256), 0, s, sb, gg, l);
     else hipLaunchKernelGGL(k_precond, dim3(8, sb.n), dim3(256), 0, s, sb, gg, l);
     if (mmode == 0 && coopG > 0) {
       int first = 1, G = coopG;
