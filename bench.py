@@ -111,8 +111,25 @@ def exact_rel_error(Q, ctx, M_cores, x, y):
     return float(np.sqrt(max(nn - 2.0 * ym + yy, 0.0) / nn))
 
 
+def left_canonical(cores):
+    """Input preparation of the kernel sweep: the random cores made left-orthonormal by
+    host QR from the left (the last core keeps the norm); the bonds do not change."""
+    out, carry = [], None
+    for k, c in enumerate(cores):
+        if carry is not None:
+            c = np.tensordot(carry, c, axes=(1, 0))
+        a, d, b = c.shape
+        if k == len(cores) - 1:
+            out.append(c)
+            break
+        q, r = np.linalg.qr(c.reshape(a * d, b))
+        out.append(q.reshape(a, d, q.shape[1]))
+        carry = r
+    return out
+
+
 def sweep(args):
-    """Isolated kernel sweep: random MPS (L = 24, cores N(0, 1/chi)) times random MPO
+    """Isolated kernel sweep: random MPS (L = 24, cores N(0, 1/chi), then left-canonical) times random MPO
     (bond w, entries N(0, 1)), zip-up apply plus rounding to chi, `trials` chains per
     call. Reports the site contractions in TFLOP/s from the library's work counters and
     HIP-event brackets, the whole apply time and, for FP64, the truncation error
@@ -125,7 +142,8 @@ def sweep(args):
     L = 24
     ctx = Q.Context(0)
     for chi in [int(c) for c in args.sweep_chi.split(",")]:
-        xs = [Q.MPS.from_cores(random_mps_cores(L, chi, seed=100 + t), chi) for t in range(args.trials)]
+        xs = [Q.MPS.from_cores(left_canonical(random_mps_cores(L, chi, seed=100 + t)), chi)
+              for t in range(args.trials)]
         for w in [int(v) for v in args.sweep_w.split(",")]:
             Ms = [Q.MPO.from_cores(random_mpo_cores(L, w, seed=200 + t)) for t in range(args.trials)]
             ys = [Q.MPS(L, chi) for _ in range(args.trials)]
