@@ -131,9 +131,11 @@ def left_canonical(cores):
 def sweep(args):
     """Isolated kernel sweep: random MPS (L = 24, cores N(0, 1/chi), then left-canonical) times random MPO
     (bond w, entries N(0, 1)), zip-up apply plus rounding to chi, `trials` chains per
-    call. Reports the site contractions in TFLOP/s from the library's work counters and
-    HIP-event brackets, the whole apply time and, for FP64, the truncation error
-    ||y - M x|| / ||M x|| of the first chain from exact inner products. In FP64 at slot capacity 64 or 128 both
+    call. Reports the whole call's time over all chains (the library runs batches of 32
+    chains up to four at a time), the site contractions in TFLOP/s from the library's
+    work counters and HIP-event brackets over one batch of (at most) 32 chains, where no
+    other batch runs beside them, and, for FP64, the truncation error ||y - M x|| / ||M x||
+    of the first chain from exact inner products. In FP64 at slot capacity 64 or 128 both
     contractions of a site run in one kernel (k_zip_fused, reported under carry_x_core,
     "fused": true); otherwise k_zip_t1 (carry_x_core) and k_zip_t2 (x_mpo_core)."""
     import torch
@@ -151,13 +153,18 @@ def sweep(args):
                 Q.apply_mpo(ctx, Ms, xs, ys, tol=0.0, chi=chi, dtype=dt, fit=0)      # warm-up
                 torch.cuda.synchronize()
                 rec = {"sweep": "apply+round", "L": L, "chi": chi, "w": w, "dtype": dt, "trials": args.trials}
+                t0 = time.perf_counter()
+                Q.apply_mpo(ctx, Ms, xs, ys, tol=0.0, chi=chi, dtype=dt, fit=0)
+                torch.cuda.synchronize()
+                rec["apply_ms"] = round(1e3 * (time.perf_counter() - t0), 3)
+                rec["chains_per_s"] = round(args.trials / (rec["apply_ms"] * 1e-3), 2)
+                nb = min(args.trials, 32)
+                rec["kernel_rates_chains"] = nb
                 for cls, tag in (("zip_contract", "carry_x_core"), ("zip_mpo", "x_mpo_core")):
                     timer = Q.KernelTimer(ctx, cls, dt)
                     timer.start()
-                    t0 = time.perf_counter()
-                    Q.apply_mpo(ctx, Ms, xs, ys, tol=0.0, chi=chi, dtype=dt, fit=0)
+                    Q.apply_mpo(ctx, Ms[:nb], xs[:nb], ys[:nb], tol=0.0, chi=chi, dtype=dt, fit=0)
                     torch.cuda.synchronize()
-                    rec["apply_ms"] = round(1e3 * (time.perf_counter() - t0), 3)
                     kt = timer.read()
                     tf = kt["flops"] / (kt["ms"] * 1e-3) / 1e12 if kt["ms"] > 0 else 0.0
                     rec[tag] = {"tflops": round(tf, 3), "frac_of_peak": round(tf / PEAKS[dt], 5),
@@ -179,14 +186,14 @@ def sweep(args):
                     # time from the per-launch brackets of the last timed apply of class 0
                     timer = Q.KernelTimer(ctx, "zip_contract", dt)
                     timer.start()
-                    Q.apply_mpo(ctx, Ms, xs, ys, tol=0.0, chi=chi, dtype=dt, fit=0)
+                    Q.apply_mpo(ctx, Ms[:nb], xs[:nb], ys[:nb], tol=0.0, chi=chi, dtype=dt, fit=0)
                     timer.read()
                     per = timer.durations()
                     xb = [min(2 ** k, 2 ** (L - k), chi) for k in range(L + 1)]
                     yb = ys[0].bonds()
                     wb = [1] + [w] * (L - 1) + [1]
                     sat = [k for k in range(L) if xb[k] == chi and xb[k + 1] == chi]
-                    fl = sum(args.trials * (4.0 * yb[k] * wb[k] * xb[k + 1] * xb[k] +
+                    fl = sum(nb * (4.0 * yb[k] * wb[k] * xb[k + 1] * xb[k] +
                                             8.0 * yb[k] * wb[k + 1] * xb[k + 1] * wb[k]) for k in sat)
                     ms = sum(per[k] for k in sat)
                     tfs = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0

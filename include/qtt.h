@@ -119,7 +119,11 @@ const char* qtt_last_error(const qtt_ctx* ctx);
 /* ---- TT algebra (Sec. 2.1) -------------------------------------------------
  * Every operation takes `n` independent problems (arrays of n descriptors) and
  * runs them together, site by site. All problems of one call share L, d and the
- * capacities. */
+ * capacities. One launch holds up to 32 problems; qtt_apply_mpo and qtt_round
+ * with more run their launch batches up to four at a time on the context's own
+ * streams, which wait for `stream` on entry and which `stream` waits for before
+ * the call returns, so the call is ordered on `stream` like a single launch
+ * sequence. */
 
 /* y_i = round(M_i x_i): MPO times MPS (Sec. 2.1.2, mat-vec with fused bond) by a
  * left-to-right zip-up that truncates each site as it is formed, a right-to-left

@@ -38,6 +38,11 @@ struct qtt_ctx {
   size_t siws_cap = 0;
   double* pool = nullptr;      // fractional-step temporaries (device)
   size_t pool_cap = 0;         // bytes
+  // side streams and events: calls with more chains than one launch holds run up to
+  // QTT_LANES launch batches at once, each on its own stream and workspace
+  hipStream_t side[QTT_LANES] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[QTT_LANES] = {};
   double* idm = nullptr;       // identity MPO cores (bond 1), for plain terms of a fit
   int* idb = nullptr;          // its bonds (all ones)
   int id_L = 0;
@@ -78,6 +83,33 @@ int fail(qtt_ctx* ctx, int code, const char* fmt, ...) {
 int launch_status(qtt_ctx* ctx) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(ctx, QTT_EHIP, "kernel launch: %s", hipGetErrorString(e));
+  return QTT_OK;
+}
+
+// Batches of a call with more than QTT_BMAX chains: batch i runs on lane i % lanes.
+// With one lane everything stays on the caller's stream; otherwise the side streams
+// first wait for the caller's stream (fork) and the caller's stream then waits for
+// each of them (join), so the call keeps the stream semantics of a single launch
+// sequence (also under graph capture).
+int lanes_for(int n) { return std::min(QTT_LANES, (n + QTT_BMAX - 1) / QTT_BMAX); }
+
+hipStream_t lane_stream(qtt_ctx* ctx, int lanes, int lane, hipStream_t s) {
+  return lanes > 1 ? ctx->side[lane] : s;
+}
+
+int lanes_fork(qtt_ctx* ctx, int lanes, hipStream_t s) {
+  if (lanes < 2) return QTT_OK;
+  HIPCHK(ctx, hipEventRecord(ctx->fork, s));
+  for (int j = 0; j < lanes; ++j) HIPCHK(ctx, hipStreamWaitEvent(ctx->side[j], ctx->fork, 0));
+  return QTT_OK;
+}
+
+int lanes_join(qtt_ctx* ctx, int lanes, hipStream_t s) {
+  if (lanes < 2) return QTT_OK;
+  for (int j = 0; j < lanes; ++j) {
+    HIPCHK(ctx, hipEventRecord(ctx->join[j], ctx->side[j]));
+    HIPCHK(ctx, hipStreamWaitEvent(s, ctx->join[j], 0));
+  }
   return QTT_OK;
 }
 
@@ -217,7 +249,12 @@ int qtt_create(int device, qtt_ctx** out) {
   ctx->coop = qtt_solver_detail::coop_capacity(device);
   // device address of this device's scratch array (the device is current here)
   e = hipGetSymbolAddress((void**)&ctx->scratch, HIP_SYMBOL(scratch));
-  if (e != hipSuccess) { delete ctx; return QTT_EHIP; }
+  for (int j = 0; j < QTT_LANES && e == hipSuccess; ++j) {
+    e = hipStreamCreateWithFlags(&ctx->side[j], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join[j], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming);
+  if (e != hipSuccess) { qtt_destroy(ctx); return QTT_EHIP; }
   *out = ctx;
   return QTT_OK;
 }
@@ -234,6 +271,11 @@ void qtt_destroy(qtt_ctx* ctx) {
   if (ctx->pool) hipFree(ctx->pool);
   if (ctx->idm) hipFree(ctx->idm);
   if (ctx->idb) hipFree(ctx->idb);
+  for (int j = 0; j < QTT_LANES; ++j) {
+    if (ctx->side[j]) hipStreamDestroy(ctx->side[j]);
+    if (ctx->join[j]) hipEventDestroy(ctx->join[j]);
+  }
+  if (ctx->fork) hipEventDestroy(ctx->fork);
   delete ctx;
 }
 
@@ -262,10 +304,12 @@ int qtt_apply_mpo(qtt_ctx* ctx, int n, const qtt_mpo* M, const qtt_mps* x, qtt_m
   hipStream_t s = (hipStream_t)stream;
   const int splits = split_for(W * capx);
   const WsLayout wl = WsLayout::make(L, std::max(capx, capy), W, splits);
-  const int chunk = std::min(n, QTT_BMAX);
-  if ((rc = ensure_ws(ctx, wl.total * chunk))) return rc;
+  const int lanes = lanes_for(n);
+  if ((rc = ensure_ws(ctx, wl.total * std::min(n, lanes * QTT_BMAX)))) return rc;
   const int chi = std::min(tr->chi_max, capy);
-  for (int i0 = 0; i0 < n; i0 += QTT_BMAX) {
+  if ((rc = lanes_fork(ctx, lanes, s))) return rc;
+  for (int i0 = 0, bi = 0; i0 < n; i0 += QTT_BMAX, ++bi) {
+    const int lane = bi % lanes;
     Batch b;
     b.n = std::min(QTT_BMAX, n - i0);
     for (int i = 0; i < b.n; ++i) {
@@ -274,13 +318,15 @@ int qtt_apply_mpo(qtt_ctx* ctx, int n, const qtt_mpo* M, const qtt_mps* x, qtt_m
       c.x = x[i0 + i].data; c.xb = x[i0 + i].bond;
       c.y = y[i0 + i].data; c.yb = y[i0 + i].bond;
       c.m = M[i0 + i].data; c.mb = M[i0 + i].bond;
-      c.ws = ctx->ws + wl.total * i;
+      c.ws = ctx->ws + wl.total * ((size_t)lane * QTT_BMAX + i);
     }
     Geo g = make_geo(L, capx, capy, wcap, W, tr->rel_tol, chi, contract_dt, capx, splits, ctx->lds);
-    zipup(b, g, wl, s);
-    rl_sweep(b, g, s);
+    const hipStream_t ls = lane_stream(ctx, lanes, lane, s);
+    zipup(b, g, wl, ls);
+    rl_sweep(b, g, ls);
   }
   if ((rc = launch_status(ctx))) return rc;
+  if ((rc = lanes_join(ctx, lanes, s))) return rc;
   // variational refinement (Sec. 2.2): fitting sweeps at the bonds chosen above
   return qtt_solver_detail::fit_sweeps(ctx, n, M, x, y, tr->fit_sweeps, contract_dt, stream);
 }
@@ -327,23 +373,27 @@ int qtt_round(qtt_ctx* ctx, int n, qtt_mps* x, const qtt_trunc* tr, void* stream
   HIPCHK(ctx, hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   const WsLayout wl = WsLayout::make(L, cap, 1, 1);
-  const int chunk = std::min(n, QTT_BMAX);
-  if ((rc = ensure_ws(ctx, wl.total * chunk))) return rc;
-  for (int i0 = 0; i0 < n; i0 += QTT_BMAX) {
+  const int lanes = lanes_for(n);
+  if ((rc = ensure_ws(ctx, wl.total * std::min(n, lanes * QTT_BMAX)))) return rc;
+  if ((rc = lanes_fork(ctx, lanes, s))) return rc;
+  for (int i0 = 0, bi = 0; i0 < n; i0 += QTT_BMAX, ++bi) {
+    const int lane = bi % lanes;
     Batch b;
     b.n = std::min(QTT_BMAX, n - i0);
     for (int i = 0; i < b.n; ++i) {
       Chain& c = b.c[i];
       std::memset(&c, 0, sizeof(c));
       c.y = x[i0 + i].data; c.yb = x[i0 + i].bond;
-      c.ws = ctx->ws + wl.total * i;
+      c.ws = ctx->ws + wl.total * ((size_t)lane * QTT_BMAX + i);
     }
     Geo g = make_geo(L, cap, cap, 1, 1, tr->rel_tol, std::min(tr->chi_max, cap), 0, cap, 1, ctx->lds);
-    qttk::ws_init(b, wl, s);
-    lr_sweep(b, g, s);
-    rl_sweep(b, g, s);
+    const hipStream_t ls = lane_stream(ctx, lanes, lane, s);
+    qttk::ws_init(b, wl, ls);
+    lr_sweep(b, g, ls);
+    rl_sweep(b, g, ls);
   }
-  return launch_status(ctx);
+  if ((rc = launch_status(ctx))) return rc;
+  return lanes_join(ctx, lanes, s);
 }
 
 int qtt_add(qtt_ctx* ctx, int n, const double* a, const qtt_mps* x, const double* bw, const qtt_mps* y,

@@ -479,38 +479,64 @@ __device__ void sym_eig(double* G, int m, int ldg, double* Z, int ldz, double* l
       bool under = false;
       double lam_up = lam[mm];                    // lam[i + 1] of the current step (old value)
       double ei = e[mm - 1], li = lam[mm - 1];     // e[i], lam[i] of the current step
-      for (int i = mm - 1; i >= l; --i) {
-        // operands of the next step, loaded ahead (not written by this iteration yet)
-        const double en = (i > l) ? e[i - 1] : 0.0, ln = (i > l) ? lam[i - 1] : 0.0;
-        const double f = sn * ei, b2 = cs * ei;
-        const double r2 = f * f + g * g;
-        if (r2 == 0.0) {
-          if (lane == 0) { e[i + 1] = 0.0; lam[i + 1] = lam_up - p; e[mm] = 0.0; }
-          under = true;
-          break;
+      // The steps i = mm-1 .. l run in chunks of 64. At the start of a chunk lane j
+      // reads the operands e[i-1], lam[i-1] of its step i = i0 - j (a step writes
+      // only entries i + 1, which no later step of the iteration reads, so these are
+      // the values the step would read), each step takes them with a lane read, and
+      // lane j keeps the outputs of step i0 - j until the chunk ends and they are
+      // stored together: no LDS access waits inside the recurrence.
+      for (int i0 = mm - 1; i0 >= l && !under; i0 -= 64) {
+        const int cn = min(64, i0 - l + 1);
+        const int ip = i0 - 1 - lane;
+        const bool has = lane < cn && ip >= l;
+        const double E = has ? e[ip] : 0.0, Lm = has ? lam[ip] : 0.0;
+        double se = 0.0, sl = 0.0, sc = 0.0, ss = 0.0;
+        const int c0 = cnt;
+        int done = 0;
+        for (int j = 0; j < cn; ++j) {
+          const double en = lane_value(E, j), ln = lane_value(Lm, j);
+          const double f = sn * ei, b2 = cs * ei;
+          const double r2 = f * f + g * g;
+          if (r2 == 0.0) {
+            under = true;
+            break;
+          }
+          // 1/sqrt(r2): hardware estimate, two Newton steps (quadratic convergence from
+          // the estimate's ~2^-26 relative error to rounding level)
+          double ir = __builtin_amdgcn_rsq(r2);
+          ir = fma(ir, fma(-0.5 * r2 * ir, ir, 0.5), ir);
+          ir = fma(ir, fma(-0.5 * r2 * ir, ir, 0.5), ir);
+          const double rr = r2 * ir;
+          sn = f * ir;
+          cs = g * ir;
+          g = lam_up - p;
+          r = (li - g) * sn + 2.0 * cs * b2;
+          p = sn * r;
+          const bool mine = lane == j;
+          se = mine ? rr : se;
+          sl = mine ? g + p : sl;
+          sc = mine ? cs : sc;
+          ss = mine ? sn : ss;
+          g = cs * r - b2;
+          ++cnt;
+          ++done;
+          lam_up = li;
+          ei = en;
+          li = ln;
         }
-        // 1/sqrt(r2): hardware estimate, two Newton steps (quadratic convergence from
-        // the estimate's ~2^-26 relative error to rounding level)
-        double ir = __builtin_amdgcn_rsq(r2);
-        ir = fma(ir, fma(-0.5 * r2 * ir, ir, 0.5), ir);
-        ir = fma(ir, fma(-0.5 * r2 * ir, ir, 0.5), ir);
-        const double rr = r2 * ir;
-        sn = f * ir;
-        cs = g * ir;
-        g = lam_up - p;
-        r = (li - g) * sn + 2.0 * cs * b2;
-        p = sn * r;
-        if (lane == 0) {
-          e[i + 1] = rr;
-          lam[i + 1] = g + p;
-          cb[cnt] = cs;
-          sb[cnt] = sn;
+        if (lane < done) {
+          e[i0 - lane + 1] = se;
+          lam[i0 - lane + 1] = sl;
+          cb[c0 + lane] = sc;
+          sb[c0 + lane] = ss;
         }
-        g = cs * r - b2;
-        ++cnt;
-        lam_up = li;
-        ei = en;
-        li = ln;
+        if (under && lane == 0) {
+          // r2 underflowed at step i0 - done: the iteration ends there
+          const int i = i0 - done;
+          e[i + 1] = 0.0;
+          lam[i + 1] = lam_up - p;
+          e[mm] = 0.0;
+        }
       }
       if (!under && lane == 0) {
         lam[l] -= p;

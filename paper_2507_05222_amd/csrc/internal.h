@@ -6,6 +6,7 @@
 #include <vector>
 
 #define QTT_BMAX 32      // chains per launch (kernel-argument job table)
+#define QTT_LANES 4      // launch batches of one call that run at once (side streams)
 
 // One chain of a batched operation: device pointers of its operands and its
 // private workspace. Unused pointers are null.

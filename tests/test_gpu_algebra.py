@@ -140,6 +140,40 @@ def test_apply_batched_matches_single(Q, ctx):
         assert rel(R.tt_full(Y[i].cores()), ref) < 1e-10
 
 
+def test_apply_and_round_over_several_launch_batches(Q, ctx):
+    """70 chains: three launch batches of at most 32, run at once on the context's
+    side streams. Each chain's arithmetic does not depend on its batch, so every
+    result equals the chain applied (and rounded) on its own, bit for bit, and the
+    dense product to rounding."""
+    L, n = 10, 70
+    xs = [random_mps_cores(L, 6, seed=300 + i) for i in range(n)]
+    Ms = [random_mpo_cores(L, 3, seed=500 + i) for i in range(n)]
+    X = [_rc(Q, ctx, c, 6) for c in xs]
+    mpos = [Q.MPO.from_cores(m) for m in Ms]
+    Y = [Q.MPS(L, 18) for _ in range(n)]
+    Q.apply_mpo(ctx, mpos, X, Y, tol=0.0, chi=18)
+    for i in (0, 31, 32, 63, 64, 69):
+        Y1 = Q.MPS(L, 18)
+        Q.apply_mpo(ctx, [mpos[i]], [X[i]], [Y1], tol=0.0, chi=18)
+        assert np.array_equal(Y1.bonds(), Y[i].bonds())
+        assert np.array_equal(Y1.data.cpu().numpy(), Y[i].data.cpu().numpy()), i
+    for i in range(n):
+        ref = R.mpo_apply_dense(Ms[i], R.tt_full(xs[i]))
+        assert rel(R.tt_full(Y[i].cores()), ref) < 1e-10, i
+    # rounding of all 70 at a tolerance, against one at a time
+    Z = [Q.MPS(L, 18) for _ in range(n)]
+    for i in range(n):
+        Z[i].copy_(Y[i])
+    Q.round_(ctx, Z, tol=1e-3, chi=18)
+    for i in (0, 33, 69):
+        Z1 = Q.MPS(L, 18)
+        Z1.copy_(Y[i])
+        Q.round_(ctx, [Z1], tol=1e-3, chi=18)
+        assert np.array_equal(Z1.bonds(), Z[i].bonds())
+        assert np.array_equal(Z1.data.cpu().numpy(), Z[i].data.cpu().numpy()), i
+        assert rel(R.tt_full(Z[i].cores()), R.tt_full(Y[i].cores())) <= 1e-3
+
+
 @pytest.mark.parametrize("tol", [1e-1, 1e-4, 1e-8])
 def test_round_error_bound(Q, ctx, tol):
     L = 12
