@@ -13,6 +13,9 @@ MFMA contractions, both tile sizes).
       --cal-fetch CF.db --cal-write CW.db --trace T.db --out profiles/....json [--kernel cg_coop]
 
 `--table T.db [N]` prints the N largest kernels of a kernel-trace database instead.
+`--overlap T.db MARKER` splits a kernel trace into calls, each starting at a launch whose
+name contains MARKER (launches of one call less than 100 ms apart), and prints per call
+the span of its library kernels, their summed durations and the streams they ran on.
 """
 from __future__ import annotations
 
@@ -82,8 +85,42 @@ def kernel_table(db, top=25):
     return "\n".join(out)
 
 
+def call_overlap(db, marker, gap_ms=100.0):
+    """Per call: (launch batches, kernels, span ms, summed kernel ms, streams). A call
+    starts at a launch named like `marker`; markers closer than gap_ms join the same
+    call, and the call's kernels are the library's (names starting with k_) launched
+    before the next call starts."""
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, start, end, stream_id from kernels order by start").fetchall()
+    marks = [r for r in rows if marker in r[0]]
+    if not marks:
+        return []
+    groups, cur = [], [marks[0]]
+    for r in marks[1:]:
+        if r[1] - cur[-1][1] < gap_ms * 1e6:
+            cur.append(r)
+        else:
+            groups.append(cur)
+            cur = [r]
+    groups.append(cur)
+    starts = [g[0][1] for g in groups] + [rows[-1][2] + 1]
+    out = []
+    for i, g in enumerate(groups):
+        ks = [r for r in rows if starts[i] <= r[1] < starts[i + 1] and short_name(r[0]).startswith("k_")]
+        span = (max(r[2] for r in ks) - min(r[1] for r in ks)) / 1e6
+        busy = sum(r[2] - r[1] for r in ks) / 1e6
+        out.append((len(g), len(ks), span, busy, sorted(set(r[3] for r in ks))))
+    return out
+
+
 def main():
     import sys
+    if len(sys.argv) >= 4 and sys.argv[1] == "--overlap":
+        print("| call | launch batches | kernels | span ms | summed kernel ms | summed / span | streams |")
+        print("|---:|---:|---:|---:|---:|---:|---|")
+        for i, (nb, nk, span, busy, st) in enumerate(call_overlap(sys.argv[2], sys.argv[3])):
+            print(f"| {i} | {nb} | {nk} | {span:.1f} | {busy:.1f} | {busy / span:.2f} | {st} |")
+        return
     if len(sys.argv) >= 3 and sys.argv[1] == "--table":
         print(kernel_table(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 25))
         return

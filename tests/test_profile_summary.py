@@ -80,3 +80,30 @@ def test_cg_kernel_pattern_and_bench_sources(tmp_path):
     n, avg = PS.trace_avg_us(db, pat)
     assert n == 2 and avg == pytest.approx(300.0)
     assert PS.source_hash(files) == bench.kernel_source_hash()
+
+
+def test_call_overlap_groups_calls_and_sums_concurrent_kernels(tmp_path):
+    c = sqlite3.connect(tmp_path / "o.db")
+    c.execute("create table kernels (name text, start integer, end integer, stream_id integer)")
+    ms = 10 ** 6
+    rows = [
+        # call 0: two batches on streams 1 and 2, each 10 ms of kernels, overlapping
+        ("void (anonymous namespace)::k_mpo_transpose(Batch, Geo, WsLayout)", 0, 1 * ms, 1),
+        ("void (anonymous namespace)::k_zip_factor(Batch, Geo, WsLayout)", 1 * ms, 10 * ms, 1),
+        ("void (anonymous namespace)::k_mpo_transpose(Batch, Geo, WsLayout)", 2 * ms, 3 * ms, 2),
+        ("void (anonymous namespace)::k_zip_factor(Batch, Geo, WsLayout)", 3 * ms, 12 * ms, 2),
+        ("__amd_rocclr_copyBuffer", 12 * ms, 13 * ms, 0),          # not a library kernel
+        # call 1, 500 ms later: one batch
+        ("void (anonymous namespace)::k_mpo_transpose(Batch, Geo, WsLayout)", 500 * ms, 501 * ms, 0),
+        ("void (anonymous namespace)::k_rl_svd(Batch, Geo, WsLayout, int)", 501 * ms, 505 * ms, 0),
+    ]
+    c.executemany("insert into kernels values (?, ?, ?, ?)", rows)
+    c.commit()
+    c.close()
+    out = PS.call_overlap(str(tmp_path / "o.db"), "k_mpo_transpose")
+    assert len(out) == 2
+    nb, nk, span, busy, st = out[0]
+    assert (nb, nk, st) == (2, 4, [1, 2])
+    assert span == pytest.approx(12.0) and busy == pytest.approx(20.0)
+    nb, nk, span, busy, st = out[1]
+    assert (nb, nk, st) == (1, 2, [0]) and span == pytest.approx(5.0) and busy == pytest.approx(5.0)
