@@ -110,8 +110,12 @@ typedef struct {
 
 typedef struct qtt_ctx qtt_ctx;
 
-/* Create a context on HIP device `device`. The context owns only its scratch
- * workspace (grown on demand, freed by qtt_destroy). */
+/* Create a context on HIP device `device`. The context owns its scratch
+ * workspace (grown on demand) and four streams of default priority with their
+ * events (used only by calls of more than 32 problems), all freed by qtt_destroy.
+ * Calls on one context share its workspace: issue them from one host thread, in
+ * the order of one stream, or synchronise between them. QTT_EHIP if a HIP call
+ * fails. */
 int qtt_create(int device, qtt_ctx** out);
 void qtt_destroy(qtt_ctx* ctx);
 const char* qtt_last_error(const qtt_ctx* ctx);

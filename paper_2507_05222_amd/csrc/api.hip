@@ -325,8 +325,9 @@ int qtt_apply_mpo(qtt_ctx* ctx, int n, const qtt_mpo* M, const qtt_mps* x, qtt_m
     zipup(b, g, wl, ls);
     rl_sweep(b, g, ls);
   }
-  if ((rc = launch_status(ctx))) return rc;
+  // join first: on a launch error the caller's stream still orders after every batch
   if ((rc = lanes_join(ctx, lanes, s))) return rc;
+  if ((rc = launch_status(ctx))) return rc;
   // variational refinement (Sec. 2.2): fitting sweeps at the bonds chosen above
   return qtt_solver_detail::fit_sweeps(ctx, n, M, x, y, tr->fit_sweeps, contract_dt, stream);
 }
@@ -392,8 +393,8 @@ int qtt_round(qtt_ctx* ctx, int n, qtt_mps* x, const qtt_trunc* tr, void* stream
     lr_sweep(b, g, ls);
     rl_sweep(b, g, ls);
   }
-  if ((rc = launch_status(ctx))) return rc;
-  return lanes_join(ctx, lanes, s);
+  if ((rc = lanes_join(ctx, lanes, s))) return rc;
+  return launch_status(ctx);
 }
 
 int qtt_add(qtt_ctx* ctx, int n, const double* a, const qtt_mps* x, const double* bw, const qtt_mps* y,

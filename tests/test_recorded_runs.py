@@ -75,3 +75,24 @@ def test_tt_transient_cylinder_matches_fd():
     assert abs(tt[w, 1].mean() - fd[w, 1].mean()) <= 1e-3 * fd[w, 1].mean()
     assert np.linalg.norm(tt[:, 1] - fd[:, 1]) <= 3e-3 * np.linalg.norm(fd[:, 1])
     assert np.linalg.norm(tt[:, 2] - fd[:, 2]) <= 5e-3 * np.linalg.norm(fd[:, 2])
+
+
+def test_steady_re40_errors_fall_with_chi_to_the_band():
+    """Steady Re = 40 cylinder, 2^8 x 2^8, 2000 steps on the FP64 path at chi = 16, 32, 48
+    (results/c2_steady_re40_chi_sweep.json), scored against the FD oracle's run of the same
+    steps: no run beats the best bond-chi approximation of the oracle's fields by more
+    than TT-SVD's quasi-optimality factor sqrt(L - 1) (tests/golden/c2_best_approximation.txt,
+    oracle only), the errors fall with chi, and at chi = 48 u, v, p and the drag are inside
+    the 3e-3 band."""
+    rec = json.load(open(os.path.join(ROOT, "results", "c2_steady_re40_chi_sweep.json")))
+    floor = {int(r[0]): r[1:] for r in np.loadtxt(os.path.join(ROOT, "tests", "golden", "c2_best_approximation.txt"))}
+    errs = {}
+    for chi in (16, 32, 48):
+        p = rec["runs"][str(chi)]["paths"]["fp64"]
+        e = [p["eps_l2_vs_oracle"][k] for k in ("u", "v", "p")]
+        errs[chi] = e
+        assert all(ei >= fi / np.sqrt(15.0) for ei, fi in zip(e, floor[chi])), (chi, e, floor[chi])
+    for k in range(3):
+        assert errs[16][k] > errs[32][k] > errs[48][k]
+    assert max(errs[48]) <= 3e-3
+    assert rec["runs"]["48"]["paths"]["fp64"]["C_D_rel_err"] <= 3e-3
