@@ -350,6 +350,28 @@ def steady(args):
                       "paths": res, "cpu_baseline": cpu}), flush=True)
 
 
+def global_residual(Q, ctx, A, x, b):
+    """||A x - b|| / ||b|| of a solve in TT form, without the cancellation of the expanded
+    form <x, A^T A x> - 2 <b, A x> + <b, b>. A x is formed exactly, core by core (the
+    mat-vec with fused bond of Sec. 2.1.2, bond w chi, built here on the host as a read-out
+    of the result, not a step of the method), A x - b is rounded by the library from the
+    explicit direct sum (Householder QR and Jacobi SVD sweeps, backward stable: the error
+    is of the order of the rounding of the terms, not of their difference), and its norm
+    is read. Needs w chi + cap(b) <= 512."""
+    prod = []
+    for m, c in zip(A.cores(), x.cores()):          # m[a][r'][r][b], c[c][r][d]
+        a, _, _, bw = m.shape
+        cl, _, cr = c.shape
+        prod.append(np.einsum("aosb,csd->acobd", m, c).reshape(a * cl, 2, bw * cr))
+    cap = max(max(p.shape[0], p.shape[2]) for p in prod)
+    ax = Q.MPS.from_cores(prod, cap)
+    r = Q.MPS(x.L, cap + b.cap)
+    Q.add(ctx, 1.0, [ax], -1.0, [b], [r], tol=1e-13, chi=cap + b.cap)
+    rr = float(Q.dot(ctx, [r], [r])[0])
+    bb = float(Q.dot(ctx, [b], [b])[0])
+    return float(np.sqrt(max(rr, 0.0) / bb))
+
+
 def run_path(Q, F, ctx, ops, U0, V0, P0, opts, warmup, steps, tag):
     import torch
     st = F.FlowState(clone(Q, U0), clone(Q, V0), clone(Q, P0))
@@ -509,11 +531,19 @@ def main():
         if name == "mixed":
             st_m = st
 
-    # roofline of the dominant kernel (the one-launch local CG) over one more step of the mixed path
+    # roofline of the dominant kernel (the one-launch local CG) over one more step of the
+    # mixed path; the step also hands out its pressure right-hand side b, so that the
+    # global residual of its pressure solve can be read beside the projected one
+    b_last = Q.MPS(L, chi)
+    mixed_b = F.step_opts(dt, tol=1e-8, chi=chi, dtype="f64", product=args.product, helm=so(4), pois=so(8),
+                          warm=ws, rhs_out=b_last)
     timer = Q.KernelTimer(ctx, "cg_coop", "f64")
     timer.start()
-    F.fractional_step(ctx, ops, st_m, mixed)
+    info_last = F.fractional_step(ctx, ops, st_m, mixed_b)
     kt = timer.read()
+    residual_last = {"projected": info_last.poisson.residual,
+                     "global": global_residual(Q, ctx, ops.mpo["P"], st_m.p, b_last),
+                     "step": "the step after the timed steps of the mixed path"}
 
     cpu, errs = None, None
     if not args.no_cpu:
@@ -573,6 +603,7 @@ def main():
                    "speedup_mixed_vs_plain": None if "plain" not in sps else round(sps["mixed"] / sps["plain"], 4),
                    "eps_l2_vs_oracle": errs, "within_3e-3": in_band,
                    "solver": {k: solver_summary(v) for k, v in infos.items()},
+                   "poisson_residual_one_step": residual_last,
                    "setup_s": round(setup_s, 2)},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -106,3 +106,23 @@ def test_solve_is_bitwise_reproducible(Q, ctx):
     (xa, ia, ra), (xb, ib, rb) = runs
     assert ia == ib and ra == rb
     assert all(np.array_equal(p, q) for p, q in zip(xa, xb))
+
+
+@pytest.mark.parametrize("chi_x,tol", [(4, 1e-3), (16, 1e-10)])
+def test_global_residual_readout_matches_dense(Q, ctx, chi_x, tol):
+    """The bench's global residual ||A x - b|| / ||b|| (exact product, rounded difference, norm)
+    against the dense residual: a bond-limited solve (large residual) and a full-rank one
+    (residual near round-off), where the expanded inner-product form would cancel."""
+    import bench
+    n = 4
+    L = 2 * n
+    A = Q.build_mpo(Q.cylinder(n, Re=100.0, dt=1e-3), Q.OP["P"])
+    Ad = R.mpo_full(A.cores())
+    bc = random_mps_cores(L, 16, seed=31)
+    b = Q.MPS.from_cores(bc, 16)
+    x = Q.MPS.from_cores(random_mps_cores(L, chi_x, seed=32), chi_x)
+    Q.poisson_solve(ctx, [A], [b], [x], Q.solve_opts(tol=tol, max_sweeps=4, max_local_iters=400, local_tol=1e-12))
+    bd = R.tt_full(bc)
+    dense = np.linalg.norm(Ad @ R.tt_full(x.cores()) - bd) / np.linalg.norm(bd)
+    g = bench.global_residual(Q, ctx, A, x, b)
+    assert abs(g - dense) <= 1e-12 + 1e-6 * dense, (g, dense)
