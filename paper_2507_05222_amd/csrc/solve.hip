@@ -849,12 +849,33 @@ struct Solver {
     j.nb = C_(1); j.sa = C_(0); j.sb = C_(0); j.sc = C_(0); j.skip = nullptr;
     j.alpha = 1.0; j.beta = 0.0;
   }
+  // A table of GEMM jobs and the largest output extents its launch has to cover.
+  struct JobSet {
+    GemmBatch g;
+    int M, N;
+  };
+  void run(const JobSet& j, int mmode) { run_jobs(j.g, j.M, j.N, mmode, s); }
+  // Two independent FP64 job tables of one step: one launch when the kernel-argument
+  // table holds both (each job keeps its own shapes; workgroups beyond a job's tiles
+  // or batch count exit at once), otherwise one launch each.
+  void run_pair(const JobSet& a, const JobSet& b) {
+    if (a.g.n + b.g.n > GB) {
+      run(a, 0);
+      run(b, 0);
+      return;
+    }
+    GemmBatch m = a.g;
+    for (int i = 0; i < b.g.n; ++i) m.j[m.n + i] = b.g.j[i];
+    m.n += b.g.n;
+    m.maxb = std::max(a.g.maxb, b.g.maxb);
+    run_jobs(m, std::max(a.M, b.M), std::max(a.N, b.N), 0, s);
+  }
 
   // LA_{k+1} from LA_k (contraction of site k): LA[(a, b)][a'] with bra index a
   // (cap cx) and ket index a' (cap ck). Steps 1-2 are shared with the projection.
-  void la_steps12(int k, int mmode) {
+  JobSet la1(int k) const {
     const int ck = g.ck, W = g.W;
-    GemmBatch g1 = batch(1), g2 = batch(g.cx);
+    GemmBatch g1 = batch(1);
     for (int i = 0; i < sb.n; ++i) {
       const SChain& c = sb.c[i];
       const double* LAk = c.ws + l.LA + (size_t)k * l.env;
@@ -864,6 +885,14 @@ struct Solver {
       a.B = Kk; a.brs = C_(2 * ck); a.bcs = C_(1);
       a.C = c.ws + l.F1; a.crs = C_(2 * ck); a.ccs = C_(1);
       a.M = B2(c.xb, k, c.ab, k); a.N = C_(2 * ck); a.K = B1(c.kxb, k);
+    }
+    return {g1, g.cx * W, 2 * ck};
+  }
+  JobSet la2(int k) const {
+    const int ck = g.ck, W = g.W;
+    GemmBatch g2 = batch(g.cx);
+    for (int i = 0; i < sb.n; ++i) {
+      const SChain& c = sb.c[i];
       GemmJob& b = g2.j[i]; one(b);    // G[a][(s',b')][c'] = Mt[(s',b')][(b,s)] F[a][(b,s)][c']
       b.A = c.ws + l.Mt + (size_t)k * 4 * W * W; b.ars = B1(c.ab, k, 2); b.acs = C_(1);
       b.B = c.ws + l.F1; b.brs = C_(ck); b.bcs = C_(1);
@@ -871,11 +900,14 @@ struct Solver {
       b.M = B1(c.ab, k + 1, 2); b.N = C_(ck); b.K = B1(c.ab, k, 2);
       b.nb = B1(c.xb, k); b.sb = B1(c.ab, k, 2 * ck); b.sc = B1(c.ab, k + 1, 2 * ck);
     }
-    run_jobs(g1, g.cx * W, 2 * ck, mmode, s);
-    run_jobs(g2, 2 * W, ck, mmode, s);
+    return {g2, 2 * W, ck};
+  }
+  void la_steps12(int k, int mmode) {
+    run(la1(k), mmode);
+    run(la2(k), mmode);
   }
   // LA_{k+1}[p][(b', q)] = sum_{(a, s')} X_k[(a, s')][p] G[(a, s')][(b', q)]
-  void la_step3(int k, int mmode) {
+  JobSet la3(int k) const {
     const int cx = g.cx, ck = g.ck, W = g.W;
     GemmBatch g3 = batch(1);
     for (int i = 0; i < sb.n; ++i) {
@@ -886,43 +918,59 @@ struct Solver {
       d.C = c.ws + l.LA + (size_t)(k + 1) * l.env; d.crs = B1(c.ab, k + 1, ck); d.ccs = C_(1);
       d.M = B1(c.xb, k + 1); d.N = B1(c.ab, k + 1, ck); d.K = B1(c.xb, k, 2);
     }
-    run_jobs(g3, cx, W * ck, mmode, s);
+    return {g3, cx, W * ck};
   }
-  void la_update(int k, int mmode = 0) {
-    la_steps12(k, mmode);
-    la_step3(k, mmode);
-  }
+  void la_step3(int k, int mmode) { run(la3(k), mmode); }
 
   // RA_k from RA_{k+1}: RA[(c, b)][c'] with bra index c (cap cx), ket index c' (cap ck)
-  void ra_update(int k, int mmode = 0) {
+  JobSet ra1(int k) const {
     const int cx = g.cx, ck = g.ck, W = g.W;
-    GemmBatch g1 = batch(1), g2 = batch(cx), g3 = batch(1);
+    GemmBatch g1 = batch(1);
     for (int i = 0; i < sb.n; ++i) {
       const SChain& c = sb.c[i];
       const double* RAn = c.ws + l.RA + (size_t)(k + 1) * l.env;
-      double* RAk = c.ws + l.RA + (size_t)k * l.env;
       const double* Xk = c.x + (size_t)k * cx * 2 * cx;
-      const double* Kk = c.kx + (size_t)k * ck * 2 * ck;
       GemmJob& a = g1.j[i]; one(a);    // F[(c,s')][(b',d')] = X[(c,s')][d] RA[d][(b',d')]
       a.A = Xk; a.ars = C_(cx); a.acs = C_(1);
       a.B = RAn; a.brs = B1(c.ab, k + 1, ck); a.bcs = C_(1);
       a.C = c.ws + l.F1; a.crs = B1(c.ab, k + 1, ck); a.ccs = C_(1);
       a.M = B1(c.xb, k, 2); a.N = B1(c.ab, k + 1, ck); a.K = B1(c.xb, k + 1);
+    }
+    return {g1, 2 * cx, W * ck};
+  }
+  JobSet ra2(int k) const {
+    const int cx = g.cx, ck = g.ck, W = g.W;
+    GemmBatch g2 = batch(cx);
+    for (int i = 0; i < sb.n; ++i) {
+      const SChain& c = sb.c[i];
       GemmJob& b = g2.j[i]; one(b);    // G[c][(b,s)][d'] = Mt2[(b,s)][(s',b')] F[c][(s',b')][d']
       b.A = c.ws + l.Mt2 + (size_t)k * 4 * W * W; b.ars = B1(c.ab, k + 1, 2); b.acs = C_(1);
       b.B = c.ws + l.F1; b.brs = C_(ck); b.bcs = C_(1);
       b.C = c.ws + l.F2; b.crs = C_(ck); b.ccs = C_(1);
       b.M = B1(c.ab, k, 2); b.N = C_(ck); b.K = B1(c.ab, k + 1, 2);
       b.nb = B1(c.xb, k); b.sb = B1(c.ab, k + 1, 2 * ck); b.sc = B1(c.ab, k, 2 * ck);
+    }
+    return {g2, 2 * W, ck};
+  }
+  JobSet ra3(int k) const {
+    const int cx = g.cx, ck = g.ck, W = g.W;
+    GemmBatch g3 = batch(1);
+    for (int i = 0; i < sb.n; ++i) {
+      const SChain& c = sb.c[i];
+      double* RAk = c.ws + l.RA + (size_t)k * l.env;
+      const double* Kk = c.kx + (size_t)k * ck * 2 * ck;
       GemmJob& d = g3.j[i]; one(d);    // RA_k[(c,b)][c'] = G[(c,b)][(s,d')] K[c'][(s,d')]
       d.A = c.ws + l.F2; d.ars = C_(2 * ck); d.acs = C_(1);
       d.B = Kk; d.brs = C_(1); d.bcs = C_(2 * ck);
       d.C = RAk; d.crs = C_(ck); d.ccs = C_(1);
       d.M = B2(c.xb, k, c.ab, k); d.N = B1(c.kxb, k); d.K = C_(2 * ck);
     }
-    run_jobs(g1, 2 * cx, W * ck, mmode, s);
-    run_jobs(g2, 2 * W, ck, mmode, s);
-    run_jobs(g3, cx * W, ck, mmode, s);
+    return {g3, cx * W, ck};
+  }
+  void ra_update(int k, int mmode = 0) {
+    run(ra1(k), mmode);
+    run(ra2(k), mmode);
+    run(ra3(k), mmode);
   }
 
   // Variational projection of M x onto the frame of the bra at site k:
@@ -955,48 +1003,75 @@ struct Solver {
     slab_sum(z, s);
   }
 
-  void lb_update(int k) {
+  JobSet lb1(int k) const {
     const int cx = g.cx, cb = g.cb;
-    GemmBatch g1 = batch(1), g2 = batch(1);
+    GemmBatch g1 = batch(1);
     for (int i = 0; i < sb.n; ++i) {
       const SChain& c = sb.c[i];
-      const double* Xk = c.x + (size_t)k * cx * 2 * cx;
       const double* Bk = c.b + (size_t)k * cb * 2 * cb;
       GemmJob& a = g1.j[i]; one(a);    // F[a][(s,g)] = Lb[a][al] B[al][(s,g)]
       a.A = c.ws + l.Lb + (size_t)k * l.envb; a.ars = C_(cb); a.acs = C_(1);
       a.B = Bk; a.brs = C_(2 * cb); a.bcs = C_(1);
       a.C = c.ws + l.F3; a.crs = C_(2 * cb); a.ccs = C_(1);
       a.M = B1(c.xb, k); a.N = C_(2 * cb); a.K = B1(c.bb, k);
+    }
+    return {g1, cx, 2 * cb};
+  }
+  JobSet lb2(int k) const {
+    const int cx = g.cx, cb = g.cb;
+    GemmBatch g2 = batch(1);
+    for (int i = 0; i < sb.n; ++i) {
+      const SChain& c = sb.c[i];
+      const double* Xk = c.x + (size_t)k * cx * 2 * cx;
       GemmJob& b = g2.j[i]; one(b);    // Lb'[p][g] = X[(a,s)][p] F[(a,s)][g]
       b.A = Xk; b.ars = C_(1); b.acs = C_(cx);
       b.B = c.ws + l.F3; b.brs = C_(cb); b.bcs = C_(1);
       b.C = c.ws + l.Lb + (size_t)(k + 1) * l.envb; b.crs = C_(cb); b.ccs = C_(1);
       b.M = B1(c.xb, k + 1); b.N = B1(c.bb, k + 1); b.K = B1(c.xb, k, 2);
     }
-    run_jobs(g1, cx, 2 * cb, 0, s);
-    run_jobs(g2, cx, cb, 0, s);
+    return {g2, cx, cb};
   }
 
-  void rb_update(int k) {
+  JobSet rb1(int k) const {
     const int cx = g.cx, cb = g.cb;
-    GemmBatch g1 = batch(1), g2 = batch(1);
+    GemmBatch g1 = batch(1);
     for (int i = 0; i < sb.n; ++i) {
       const SChain& c = sb.c[i];
-      const double* Xk = c.x + (size_t)k * cx * 2 * cx;
       const double* Bk = c.b + (size_t)k * cb * 2 * cb;
       GemmJob& a = g1.j[i]; one(a);    // F[(al,s)][d] = B[(al,s)][g] Rb[d][g]
       a.A = Bk; a.ars = C_(cb); a.acs = C_(1);
       a.B = c.ws + l.Rb + (size_t)(k + 1) * l.envb; a.brs = C_(1); a.bcs = C_(cb);
       a.C = c.ws + l.F3; a.crs = C_(cx); a.ccs = C_(1);
       a.M = B1(c.bb, k, 2); a.N = B1(c.xb, k + 1); a.K = B1(c.bb, k + 1);
+    }
+    return {g1, 2 * cb, cx};
+  }
+  JobSet rb2(int k) const {
+    const int cx = g.cx, cb = g.cb;
+    GemmBatch g2 = batch(1);
+    for (int i = 0; i < sb.n; ++i) {
+      const SChain& c = sb.c[i];
+      const double* Xk = c.x + (size_t)k * cx * 2 * cx;
       GemmJob& b = g2.j[i]; one(b);    // Rb[c][al] = X[c][(s,d)] F[(al,s)][d]
       b.A = Xk; b.ars = C_(2 * cx); b.acs = C_(1);
       b.B = c.ws + l.F3; b.brs = C_(1); b.bcs = C_(2 * cx);
       b.C = c.ws + l.Rb + (size_t)k * l.envb; b.crs = C_(cb); b.ccs = C_(1);
       b.M = B1(c.xb, k); b.N = B1(c.bb, k); b.K = C_(2 * cx);
     }
-    run_jobs(g1, 2 * cb, cx, 0, s);
-    run_jobs(g2, cx, cb, 0, s);
+    return {g2, cx, cb};
+  }
+  // The operator and right-hand-side environments of a site (FP64) do not depend on
+  // each other (F1/F2 and F3 are separate buffers): their first and second steps
+  // share launches, three launches instead of five.
+  void left_envs(int k) {
+    run_pair(la1(k), lb1(k));
+    run_pair(la2(k), lb2(k));
+    run(la3(k), 0);
+  }
+  void right_envs(int k) {
+    run_pair(ra1(k), rb1(k));
+    run_pair(ra2(k), rb2(k));
+    run(ra3(k), 0);
   }
 
   void beff(int k) {
@@ -1248,7 +1323,7 @@ extern "C" int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qt
     hipLaunchKernelGGL(k_env_init, dim3(S.sb.n), dim3(256), 0, s, S.sb, S.g, lay);
     // right-canonical start (bond structure kept), right environments
     for (int k = L - 1; k >= 1; --k) S.rl_move(k);
-    for (int k = L - 1; k >= 1; --k) { S.ra_update(k); S.rb_update(k); }
+    for (int k = L - 1; k >= 1; --k) S.right_envs(k);
 
     // ||b||^2 once (FP64); the absolute floor of each local residual is a share of
     // the global target
@@ -1284,15 +1359,13 @@ extern "C" int qtt_poisson_solve(qtt_ctx* ctx, int n, const qtt_mpo* A, const qt
         S.local_solve(k, S.mode);
         if (k < L - 1) {
           S.lr_move(k);
-          S.la_update(k);
-          S.lb_update(k);
+          S.left_envs(k);
         }
       }
       // right-to-left half sweep
       for (int k = L - 1; k >= 1; --k) {
         S.rl_move(k);
-        S.ra_update(k);
-        S.rb_update(k);
+        S.right_envs(k);
         S.local_solve(k - 1, S.mode);
       }
       ++sweeps;
