@@ -545,7 +545,9 @@ def main():
     info_last = F.fractional_step(ctx, ops, st_m, mixed_b)
     kt = timer.read()
     residual_last = None
-    if not args.no_residual:
+    if not args.no_residual and int(max(ops.mpo["P"].bond_host)) * chi + b_last.cap > 512:
+        residual_last = {"skipped": "w chi + chi exceeds the 512 capacity of qtt_add"}
+    elif not args.no_residual:
         residual_last = {"projected": info_last.poisson.residual,
                          "global": global_residual(Q, ctx, ops.mpo["P"], st_m.p, b_last),
                          "step": "the step after the timed steps of the mixed path"}
