@@ -350,6 +350,17 @@ def steady(args):
                       "paths": res, "cpu_baseline": cpu}), flush=True)
 
 
+def exact_product_cores(mpo_cores, mps_cores):
+    """Cores of M x with fused bonds (Sec. 2.1.2), no truncation: core k is
+    sum_r M_k[a][r'][r][b] x_k[c][r][d] with left bond (a, c) and right bond (b, d)."""
+    prod = []
+    for m, c in zip(mpo_cores, mps_cores):
+        a, _, _, bw = m.shape
+        cl, _, cr = c.shape
+        prod.append(np.einsum("aosb,csd->acobd", m, c).reshape(a * cl, 2, bw * cr))
+    return prod
+
+
 def global_residual(Q, ctx, A, x, b):
     """||A x - b|| / ||b|| of a solve in TT form, without the cancellation of the expanded
     form <x, A^T A x> - 2 <b, A x> + <b, b>. A x is formed exactly, core by core (the
@@ -358,11 +369,7 @@ def global_residual(Q, ctx, A, x, b):
     explicit direct sum (Householder QR and Jacobi SVD sweeps, backward stable: the error
     is of the order of the rounding of the terms, not of their difference), and its norm
     is read. Needs w chi + cap(b) <= 512."""
-    prod = []
-    for m, c in zip(A.cores(), x.cores()):          # m[a][r'][r][b], c[c][r][d]
-        a, _, _, bw = m.shape
-        cl, _, cr = c.shape
-        prod.append(np.einsum("aosb,csd->acobd", m, c).reshape(a * cl, 2, bw * cr))
+    prod = exact_product_cores(A.cores(), x.cores())
     cap = max(max(p.shape[0], p.shape[2]) for p in prod)
     ax = Q.MPS.from_cores(prod, cap)
     r = Q.MPS(x.L, cap + b.cap)
